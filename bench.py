@@ -1,0 +1,351 @@
+#!/usr/bin/env python
+"""Benchmark of the masked 4D Gaussian rasterizer on one MI355X.
+
+Headline step: render one 1352x1014 frame of a 200k-Gaussian long-lifespan
+scene (20 cameras on a 120-degree arc, 300 timestamps) through the whole
+forward path: keyframe active set (one mask per 10-frame window, built before
+timing) -> slice/project/shade -> visible compaction -> depth sort -> tile
+keys -> tile sort -> ranges -> per-tile blending.  value = frames/s over
+--steps frames, inputs resident in HBM.
+
+Beside it on the same JSON line: the unfiltered 3M-Gaussian dense baseline,
+the mask on/off x temporal-cull on/off grid, forward+backward ms/iter
+(500k Gaussians, 4 views), mask build time, per-stage event timings with
+roofline fractions, and the FP64 CPU oracle timed on a sample of the frame.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/sec at 1352×1014, masked vs dense; fwd+bwd ms/iter @ ≤1e-4 img err"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# fp32 operations the compositor spends on one evaluated (pixel, Gaussian) pair
+# on the skip path: offset (2), quadratic form (7), exp2 (1), opacity (1),
+# clamp (1), alpha test (1), transmittance test (3).
+FLOPS_PER_PAIR = 16
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def stage_bytes(name, prof, frames, masked, pixels):
+    """Algorithmic HBM bytes a stage must move over the profiled frames."""
+    P, V, M = prof["processed"], prof["visible"], prof["instances"]
+    if name == "preprocess":
+        return P * (68 + (4 if masked else 0) + 4) + V * (192 + 48)
+    if name == "compact":
+        return P * (1 + 4) + V * 8
+    if name == "depth_sort":
+        return V * 16 * 4
+    if name == "offsets":
+        return V * (4 + 4 + 8)
+    if name == "duplicate":
+        return V * 16 + M * 8
+    if name == "tile_sort":
+        return M * 16 * 2
+    if name == "ranges":
+        return M * 4
+    if name == "composite":
+        return M * 40 + frames * pixels * 12
+    return 0
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current source of that kernel."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    src = os.path.join(ROOT, "paper_2503_16422_amd", "csrc", d.get("source", ""))
+    if not os.path.exists(src) or source_sha(src) != d.get("source_sha"):
+        return None
+    return d.get("bytes_per_launch")
+
+
+def build_masks(ctx, model, cams, n_frames=300, interval=10, mode=1):
+    from paper_2503_16422_amd import inputs
+    frames = inputs.frame_times(n_frames)
+    keys, windows, frame_window = inputs.keyframe_windows(n_frames, interval)
+    masks = []
+    sync()
+    t0 = time.perf_counter()
+    for lo, hi in windows:
+        bits, idx, count = ctx.build_active_mask(model, frames[lo:hi + 1], frames[lo], frames[hi], mode, cams)
+        masks.append((idx, count))
+    sync()
+    ms = (time.perf_counter() - t0) * 1e3 / len(windows)
+    kept = [int(c.item()) for _, c in masks]
+    return masks, frame_window, frames, ms, kept
+
+
+def frame_schedule(k, n_cams, n_frames):
+    return k % n_cams, (k * 37 + 11) % n_frames
+
+
+def run_frames(ctx, model, cams, frames, masks, frame_window, cfg, steps, start, out):
+    for k in range(start, start + steps):
+        c, f = frame_schedule(k, len(cams), len(frames))
+        if masks is None:
+            ctx.render(model, cams[c], float(frames[f]), cfg, out_rgb=out)
+        else:
+            idx, cnt = masks[frame_window[f]]
+            ctx.render(model, cams[c], float(frames[f]), cfg, idx=idx, n_idx=cnt, out_rgb=out)
+
+
+def max_instances(ctx, model, cams, frames, masks, frame_window, cfg, steps, start):
+    """Exact instance counts of the frames a timed loop will render."""
+    from paper_2503_16422_amd import _lib
+    worst = 0
+    for k in range(start, start + steps):
+        c, f = frame_schedule(k, len(cams), len(frames))
+        kw = {}
+        if masks is not None:
+            idx, cnt = masks[frame_window[f]]
+            kw = dict(idx=idx, n_idx=cnt)
+        _, _, st = ctx.render(model, cams[c], float(frames[f]), cfg, keep_state=True, **kw)
+        worst = max(worst, ctx.binning(st)["n_inst"])
+        ctx.release(st)
+    return worst
+
+
+def timed_fps(ctx, model, cams, frames, masks, frame_window, cfg, steps, warmup, out, start=0):
+    run_frames(ctx, model, cams, frames, masks, frame_window, cfg, warmup, start, out)
+    sync()
+    t0 = time.perf_counter()
+    run_frames(ctx, model, cams, frames, masks, frame_window, cfg, steps, start + warmup, out)
+    sync()
+    dt = time.perf_counter() - t0
+    ctx.check_overflow()
+    return steps / dt, dt
+
+
+def cpu_baseline(scene, idx, cam, t, row_step):
+    """FP64 oracle (C, OpenMP, rect mode) on every row_step-th row of one frame."""
+    import numpy as np
+    from oracle import composite as oc
+    f32 = lambda x: float(np.float32(x))
+    st = oc.Settings(alpha_min=f32(1 / 255), alpha_max=f32(0.99), t_min=f32(1e-4), dilation=f32(0.3))
+    rows = np.arange(0, cam.height, row_step)
+    py, px = np.meshgrid(rows, np.arange(cam.width), indexing="ij")
+    t0 = time.perf_counter()
+    pre = oc.prepare(scene.arrays(), cam, t, st, idx=idx)
+    oc.composite(pre, cam, st, mode="rect", pixels=(px.ravel(), py.ravel()))
+    dt = time.perf_counter() - t0
+    frac = rows.size / cam.height
+    return {"value": frac / dt, "unit": "frames/s", "cores": oc.num_threads(), "kind": "oracle",
+            "sample": f"{rows.size} of {cam.height} rows (every {row_step}th) of one masked 1352x1014 frame, "
+                      f"{idx.size} Gaussians, FP64 slice+project+SH then rect-mode per-pixel blending; "
+                      f"{dt:.1f} s wall, scaled to whole frames",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def fwd_bwd(ctx, steps, warmup):
+    import numpy as np
+    import torch
+    from paper_2503_16422_amd import _lib, inputs
+    from paper_2503_16422_amd.render import GaussianModel
+    sc = inputs.dense_scene(500_000, seed=0)
+    tgt = inputs.dense_scene(500_000, seed=1)
+    cams = inputs.arc_cameras(20, 4.0, 1352, 1014)
+    rng = np.random.default_rng(2)
+    views = [(int(c), float(t)) for c, t in zip(rng.choice(20, 4, replace=False), rng.uniform(0, 1, 4))]
+    model = GaussianModel.from_scene(sc, "cuda:0")
+    tmodel = GaussianModel.from_scene(tgt, "cuda:0")
+    cfg = _lib.default_cfg()
+    targets = [ctx.render(tmodel, cams[c], t, cfg)[0].clone() for c, t in views]
+    grads = {k: torch.zeros_like(getattr(model, k)) for k in GaussianModel.FIELDS}
+    states = [None] * 4
+
+    def step():
+        for g in grads.values():
+            g.zero_()
+        loss = 0.0
+        for v, (c, t) in enumerate(views):
+            rgb, _, states[v] = ctx.render(model, cams[c], t, cfg, keep_state=states[v] or True)
+            dL = rgb - targets[v]
+            ctx.backward(states[v], dL, model, grads)
+        return loss
+
+    for _ in range(warmup):
+        step()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    sync()
+    dt = time.perf_counter() - t0
+    for s in states:
+        ctx.release(s)
+    return dt * 1e3 / steps, views
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the masked headline loop (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build renders every view on a single MI355X and has no "
+              "multi-GPU path (--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2503_16422_amd import _lib, inputs
+    from paper_2503_16422_amd.render import Context, GaussianModel
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = Context(0)
+    W, H = 1352, 1014
+    cams = inputs.arc_cameras(20, 4.0, W, H)
+    out = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+
+    # ---- headline: masked 200k scene -------------------------------------------------
+    log("[bench] masked scene: generating 200k Gaussians")
+    scene = inputs.long_scene(200_000, seed=0)
+    model = GaussianModel.from_scene(scene, "cuda:0")
+    masks, frame_window, frames, mask_ms, kept = build_masks(ctx, model, cams)
+    log(f"[bench] masks: {len(masks)} windows, {mask_ms:.2f} ms/window, kept mean {np.mean(kept):.0f}")
+    cfg = _lib.default_cfg()
+    K, Wu = args.steps, args.warmup
+    worst = max_instances(ctx, model, cams, frames, masks, frame_window, cfg, K + Wu, 0)
+    cfg = _lib.default_cfg(instance_capacity=int(worst * 1.05) + 4096)
+    log(f"[bench] max instances over the timed frames {worst}")
+    fps, dt = timed_fps(ctx, model, cams, frames, masks, frame_window, cfg, K, Wu, out)
+    log(f"[bench] masked: {fps:.1f} frames/s ({dt * 1e3 / K:.3f} ms/frame)")
+
+    # same frames again with stage events
+    ctx.profile(True)
+    run_frames(ctx, model, cams, frames, masks, frame_window, cfg, K, Wu, out)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    stages = {}
+    for name in _lib.STAGES[:8]:
+        calls = prof["calls"][name]
+        if not calls:
+            continue
+        avg_ms = prof["ms"][name] / calls
+        nbytes = stage_bytes(name, prof, K, True, W * H)
+        entry = {"avg_ms": round(avg_ms, 5), "algorithmic_GBps": round(nbytes / calls / (avg_ms * 1e-3) / 1e9, 1)}
+        entry["hbm_frac"] = round(entry["algorithmic_GBps"] / HBM_PEAK_GBS, 4)
+        stages[name] = entry
+    comp = stages["composite"]
+    pairs_per_frame = prof["pairs"] / K
+    comp_tflops = pairs_per_frame * FLOPS_PER_PAIR / (comp["avg_ms"] * 1e-3) / 1e12
+    comp["pairs_per_frame"] = int(pairs_per_frame)
+    comp["achieved_TFLOPs"] = round(comp_tflops, 3)
+    dominant = max(stages, key=lambda s: stages[s]["avg_ms"])
+    if dominant == "composite":
+        roof = {"bound": "alu", "kernel": "composite_kernel<16,16,128>", "achieved": round(comp_tflops, 3),
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(comp_tflops / FP32_PEAK_TFLOPS, 4),
+                "traffic": load_traffic("composite")}
+    else:
+        e = stages[dominant]
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": e["algorithmic_GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": e["hbm_frac"], "traffic": load_traffic(dominant)}
+    per_frame = {"processed": prof["processed"] / K, "visible": prof["visible"] / K,
+                 "instances": prof["instances"] / K}
+    log(f"[bench] stages: {json.dumps(stages)}")
+
+    extra = {}
+    if not args.headline_only:
+        # ---- mask on/off x temporal cull on/off on the same scene ---------------------
+        grid = {}
+        n_grid = 60
+        for use_mask in (True, False):
+            for cull in (1, 0):
+                c0 = _lib.default_cfg(temporal_cull=cull)
+                f, _ = timed_fps(ctx, model, cams, frames, masks if use_mask else None, frame_window, c0,
+                                 n_grid, 5, out, start=1000)
+                grid[f"mask={'on' if use_mask else 'off'},cull={'on' if cull else 'off'}"] = round(f, 1)
+        log(f"[bench] grid: {grid}")
+        extra["masked_scene_grid_fps"] = grid
+
+        # ---- dense unfiltered 3M scene -----------------------------------------------
+        del model
+        torch.cuda.empty_cache()
+        log("[bench] dense scene: generating 3M Gaussians")
+        dense = inputs.dense_scene(3_000_000, seed=0)
+        dmodel = GaussianModel.from_scene(dense, "cuda:0")
+        del dense
+        n_dense = 16
+        vanilla = _lib.default_cfg(temporal_cull=0)
+        d_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, vanilla, n_dense, 3, out, start=2000)
+        dc_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, _lib.default_cfg(), n_dense, 3, out,
+                              start=2000)
+        dmasks, dfw, _, dmask_ms, dkept = build_masks(ctx, dmodel, cams)
+        dm_fps, _ = timed_fps(ctx, dmodel, cams, frames, dmasks, dfw, _lib.default_cfg(), 60, 5, out, start=2000)
+        log(f"[bench] dense: vanilla {d_fps:.1f}, +cull {dc_fps:.1f}, +mask {dm_fps:.1f} frames/s")
+        extra["dense_3M"] = {"vanilla_fps": round(d_fps, 2), "temporal_cull_fps": round(dc_fps, 2),
+                             "masked_fps": round(dm_fps, 2), "mask_build_ms_per_window": round(dmask_ms, 2),
+                             "kept_mean": int(np.mean(dkept))}
+        extra["masked_200k_vs_dense_3M_vanilla"] = round(fps / d_fps, 2)
+        del dmodel, dmasks
+        torch.cuda.empty_cache()
+
+        # ---- forward + backward ------------------------------------------------------
+        log("[bench] fwd+bwd: 500k Gaussians, 4 views")
+        ms_iter, views = fwd_bwd(ctx, 20, 5)
+        extra["fwd_bwd_ms_per_iter"] = round(ms_iter, 3)
+        extra["fwd_bwd_config"] = {"gaussians": 500_000, "views": views, "resolution": [W, H],
+                                   "loss": "0.5*sum((I-I*)^2), targets rendered from a second seed"}
+        log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter")
+
+    cpu = None
+    if not args.no_cpu_baseline and not args.headline_only:
+        f = 137
+        idx, cnt = masks[frame_window[f]]
+        sel = idx[: int(cnt.item())].cpu().numpy().view(np.uint32).astype(np.int64)
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(scene, sel, cams[11], float(frames[f]), row_step=8)
+        log(f"[bench] cpu baseline {cpu['value']:.4f} frames/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": Wu,
+        "ms_per_step": round(1e3 / fps, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (per-Gaussian geometry f64)", "data": "synthetic",
+        "config": {"workload": "masked 4D Gaussian frame: 200k long-lifespan Gaussians (log s_t~N(-1,0.4)), "
+                               "1352x1014, 20 cameras x 300 timestamps, keyframe masks every 10 frames "
+                               "(temporal and tile predicate), 16x16 tiles, batch 128",
+                   "gaussians": 200_000, "resolution": [W, H], "mask_windows": len(masks),
+                   "kept_per_window_mean": int(np.mean(kept)), "per_frame": per_frame,
+                   "mask_build_ms_per_window": round(mask_ms, 3)},
+        "roofline": roof,
+        "stages": stages,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,280 @@
+/*
+ * fdgs.h - C ABI of libfdgs.so, a masked 4D Gaussian rasterizer for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library renders I(u, v, t) of a set of 4D Gaussians (Sec. 3):
+ *   - temporal slicing of every processed Gaussian into a conditional 3D
+ *     Gaussian and a temporal opacity factor (Eq. 1, Eq. 3);
+ *   - an optional keyframe active set that drops inactive Gaussians before any
+ *     of that work (Sec. 4.2.2);
+ *   - projection, screen-tile binning, depth ordering and front-to-back alpha
+ *     blending (Eq. 2, Eq. 3);
+ *   - the adjoint of the whole forward pass.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an fdgs_status.  On failure fdgs_last_error() returns
+ *     a message (thread-local, valid until the next fdgs_* call on the thread).
+ *   - Arguments are validated on the host before anything is enqueued; an
+ *     invalid argument enqueues nothing.
+ *   - "device" pointers are HIP device memory owned by the caller; the library
+ *     never frees them.  "host" pointers are ordinary CPU memory read during the
+ *     call only.
+ *   - Work is enqueued on the caller's stream and runs asynchronously unless a
+ *     call says it synchronises.
+ *   - A context owns scratch memory and is not thread-safe: use one context per
+ *     host thread / stream.
+ *   - Model tensors are float32 structure-of-arrays with plane stride n
+ *     (see fdgs_model).  Non-finite parameters or a quaternion with
+ *     |q|^2 < 1e-12 make a Gaussian invisible; they never raise an error.
+ */
+#ifndef FDGS_H
+#define FDGS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDGS_API __attribute__((visibility("default")))
+
+typedef int32_t fdgs_status;
+enum {
+    FDGS_OK = 0,
+    FDGS_ERR_INVALID_ARG = 1,   /* bad pointer, size, enum or shape          */
+    FDGS_ERR_HIP = 2,           /* a HIP runtime call failed                  */
+    FDGS_ERR_CAPACITY = 3,      /* fixed instance capacity was too small      */
+    FDGS_ERR_UNSUPPORTED = 4,   /* valid request this build does not support  */
+    FDGS_ERR_STATE = 5          /* state handle missing, released or mismatched */
+};
+
+FDGS_API const char *fdgs_last_error(void);
+FDGS_API const char *fdgs_version(void);
+
+typedef struct fdgs_ctx fdgs_ctx;
+
+/* Create a context on HIP device `device` (made current for the call). */
+FDGS_API fdgs_status fdgs_create(fdgs_ctx **out, int32_t device);
+/* Destroy a context and every state it owns.  Waits for its work to finish. */
+FDGS_API fdgs_status fdgs_destroy(fdgs_ctx *ctx);
+
+/*
+ * 4D Gaussians (Sec. 3): mean mu in R^4, covariance Sigma = R S S^T R^T with
+ * S = diag(exp(log_scale)) and R the 4D rotation x -> q_l * x * q_r (x read as
+ * a quaternion (w, i, j, k) = (x, y, z, t); both quaternions are normalised
+ * before use), opacity sigmoid(opacity_logit), RGB colour from real spherical
+ * harmonics of degree sh_degree.  All device, float32, plane stride n:
+ *   mean[4][n], log_scale[4][n], q_left[4][n], q_right[4][n] (w, x, y, z),
+ *   opacity_logit[n], sh[16][3][n] (basis k = l*l + l + m, then channel).
+ */
+typedef struct {
+    const float *mean;
+    const float *log_scale;
+    const float *q_left;
+    const float *q_right;
+    const float *opacity_logit;
+    const float *sh;
+    int64_t n;              /* 0 <= n < 2^31 */
+    int32_t sh_degree;      /* 0..3; coefficients k >= (degree+1)^2 are not read */
+} fdgs_model;
+
+/*
+ * Pinhole camera, host POD, float64.  World to camera: x_c = R x_w + tvec
+ * (R row-major), OpenCV axes (x right, y down, z forward).  Pixel (px, py) is
+ * sampled at (px + 0.5, py + 0.5); u = fx x/z + cx, v = fy y/z + cy.  A
+ * Gaussian whose conditional mean has z <= znear is not drawn.
+ */
+typedef struct {
+    double R[9];
+    double tvec[3];
+    double fx, fy, cx, cy;
+    double znear;           /* > 0 */
+    int32_t width, height;  /* 1..16384 */
+} fdgs_camera;
+
+/*
+ * Rendering options.  fdgs_render_cfg_default() fills the defaults given in
+ * brackets.  Screen tiles and the LDS batch only change speed, never the image.
+ */
+typedef struct {
+    int32_t tile_w, tile_h;     /* one of 8x8, 16x16, 32x8            [16x16] */
+    int32_t batch;              /* Gaussians staged in LDS: 64/128/256   [128] */
+    float bg[3];                /* background, added with the final T  [0,0,0] */
+    float alpha_min;            /* alpha below this is skipped         [1/255] */
+    float alpha_max;            /* alpha clamp                          [0.99] */
+    float t_min;                /* stop before T would fall below this  [1e-4] */
+    float dilation;             /* added to Sigma_2D's diagonal, px^2    [0.3] */
+    int32_t temporal_cull;      /* 1: drop sigma*p(t) < alpha_min before binning;
+                                   0: bin every Gaussian in view (the
+                                   unfiltered baseline's work)            [1] */
+    int64_t instance_capacity;  /* 0: size tile-list buffers exactly (one
+                                   host synchronisation per frame); >0: fixed
+                                   capacity, no synchronisation, overflow
+                                   reported as FDGS_ERR_CAPACITY by
+                                   fdgs_check_overflow                     [0] */
+} fdgs_render_cfg;
+
+FDGS_API void fdgs_render_cfg_default(fdgs_render_cfg *cfg);
+
+/*
+ * (1) Temporal slicing, Eq. 1 and Eq. 3.  For each j < m, Gaussian
+ * g = idx ? idx[j] : j is sliced at time t:
+ *   out_mean3[3][m]  mu_{1:3} + Sigma_{1:3,4} Sigma_44^{-1} (t - mu_t)
+ *   out_cov3[6][m]   Sigma_{1:3,1:3} - Sigma_{1:3,4} Sigma_44^{-1} Sigma_{4,1:3},
+ *                    stored xx, xy, xz, yy, yz, zz
+ *   out_p[m]         exp(-(t - mu_t)^2 / (2 Sigma_44))
+ * Computed in float64, stored float32.  An invalid Gaussian yields zeros.
+ * idx (device, uint32, entries < n) may be NULL (then m <= n).  All outputs
+ * are device buffers of the stated sizes.
+ */
+FDGS_API fdgs_status fdgs_slice_4d(fdgs_ctx *ctx, const fdgs_model *model, double t,
+                          const uint32_t *idx, int64_t m,
+                          float *out_mean3, float *out_cov3, float *out_p,
+                          hipStream_t stream);
+
+/*
+ * (2) Active set of one keyframe window (Sec. 4.2.2).
+ *   mode FDGS_MASK_TEMPORAL: keep Gaussian i iff its temporal opacity p_i(t)
+ *     reaches alpha_min at one of the window's frames (decided in float64 as
+ *     (t_f - mu_t)^2 <= 2 ln(1/alpha_min) Sigma_44).  Rendering any frame of
+ *     the window with this set gives exactly the unmasked image.
+ *   mode FDGS_MASK_TEMPORAL_AND_TILE: additionally keep only Gaussians whose
+ *     opacity-free footprint (level 2 ln(1/alpha_min)) covers a pixel of one of
+ *     the mask views at key_lo or key_hi.
+ * Outputs (device): out_bits[ceil(n/32)] (bit i%32 of word i/32, LSB first),
+ * out_idx[n] (kept indices ascending; entries past the count are unspecified)
+ * and *out_count (int64).  Synchronises `stream` (the host arrays of the spec
+ * are copied to the device during the call).
+ */
+enum { FDGS_MASK_TEMPORAL = 0, FDGS_MASK_TEMPORAL_AND_TILE = 1 };
+typedef struct {
+    const double *frame_times;  /* host, n_frames >= 1 (<= 256)              */
+    int32_t n_frames;
+    const fdgs_camera *views;   /* host, n_views mask views (mode 1 only)     */
+    int32_t n_views;            /* <= 64                                      */
+    double key_lo, key_hi;      /* keyframe times of the window               */
+    int32_t mode;
+    float alpha_min;            /* threshold on p(t) [1/255 if <= 0]          */
+    float dilation;             /* footprint dilation (mode 1) [0.3 if < 0]   */
+} fdgs_mask_spec;
+
+FDGS_API fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model,
+                                   const fdgs_mask_spec *spec,
+                                   uint32_t *out_bits, uint32_t *out_idx,
+                                   int64_t *out_count, hipStream_t stream);
+
+/*
+ * (3) Forward render of one view at time t (Eq. 2, Eq. 3).
+ * Processed set: every Gaussian if idx == NULL, else idx[0..count) with count
+ * read from the device scalar *n_idx_dev (int64, <= model->n), as written by
+ * fdgs_build_active_mask.  Per pixel the processed Gaussians that survive
+ * culling are blended front to back in order of camera depth (float64 z of the
+ * conditional mean), equal depths by processing position.
+ * Outputs (device): out_rgb[3][H][W]; out_T[H][W] (final transmittance) may be
+ * NULL.  keep_state: NULL to discard the intermediate state; otherwise
+ * *keep_state receives a state for fdgs_render_backward / inspection (a
+ * non-NULL *keep_state from an earlier forward of this context is reused).
+ */
+typedef struct fdgs_state fdgs_state;
+
+FDGS_API fdgs_status fdgs_render_forward(fdgs_ctx *ctx, const fdgs_model *model,
+                                const uint32_t *idx, const int64_t *n_idx_dev,
+                                const fdgs_camera *cam, double t,
+                                const fdgs_render_cfg *cfg,
+                                float *out_rgb, float *out_T,
+                                fdgs_state **keep_state, hipStream_t stream);
+
+/*
+ * (4) Adjoint of the forward pass recorded in `state`.  dL_drgb (device,
+ * [3][H][W]) is the gradient of a scalar loss with respect to out_rgb.
+ * Gradients are ACCUMULATED (+=) into the caller's device buffers, laid out
+ * like fdgs_model: mean[4][n], log_scale[4][n], q_left[4][n], q_right[4][n],
+ * opacity_logit[n], sh[16][3][n].  Gaussians that were not processed or not
+ * visible receive nothing.  The model passed to the forward must be unchanged.
+ * Float atomics make the last bits order-dependent.
+ */
+typedef struct {
+    float *mean, *log_scale, *q_left, *q_right, *opacity_logit, *sh;
+} fdgs_grads;
+
+FDGS_API fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state,
+                                 const float *dL_drgb, const fdgs_grads *grads,
+                                 hipStream_t stream);
+
+/* Release a state (NULL is accepted). */
+FDGS_API fdgs_status fdgs_state_release(fdgs_ctx *ctx, fdgs_state *state);
+
+/*
+ * Inspection of a state's binning (device pointers valid until the state is
+ * reused or released).  Synchronises `stream` to read the counts.
+ *   sorted_ids[n_inst]   processing positions, tile after tile, each tile in
+ *                        depth order
+ *   tile_ranges[n_tiles][2]  [start, end) of each tile (id ty*tiles_x + tx)
+ *   rects[n_proc][4]     int32 inclusive pixel rect (x0,y0,x1,y1) of each
+ *                        processed Gaussian; only meaningful when visible
+ *   depth[n_proc]        float64 camera depth of each processed Gaussian
+ *   visible[n_proc]      uint8 1 if binned
+ */
+typedef struct {
+    const uint32_t *sorted_ids;
+    const uint32_t *tile_ranges;
+    const int32_t *rects;
+    const double *depth;
+    const uint8_t *visible;
+    int64_t n_inst, n_vis, n_proc;
+    int32_t n_tiles, tiles_x, tiles_y;
+} fdgs_binning;
+
+FDGS_API fdgs_status fdgs_state_binning(fdgs_ctx *ctx, fdgs_state *state, fdgs_binning *out,
+                               hipStream_t stream);
+
+/*
+ * Reports FDGS_ERR_CAPACITY if a forward with a fixed instance_capacity on
+ * this context overflowed since the last check, or FDGS_ERR_UNSUPPORTED if
+ * more than 4096 visible Gaussians of one forward shared a float32-rounded
+ * depth (their relative order then falls back to processing order instead of
+ * the float64 depth); clears the flags.  Synchronises `stream`.
+ */
+FDGS_API fdgs_status fdgs_check_overflow(fdgs_ctx *ctx, hipStream_t stream);
+
+/*
+ * Per-stage timing with HIP events recorded on the caller's stream around each
+ * kernel group of fdgs_render_forward / fdgs_render_backward, plus work
+ * counters (processed and visible Gaussians, tile instances, and (pixel,
+ * Gaussian) pairs evaluated by the compositor).  Profiling adds event records
+ * between kernels and a per-wavefront counter update in the compositor; it is
+ * off by default.
+ */
+enum {
+    FDGS_STAGE_PREPROCESS = 0,   /* slice + project + SH + footprint        */
+    FDGS_STAGE_COMPACT = 1,      /* visible-set scan and scatter             */
+    FDGS_STAGE_DEPTH_SORT = 2,   /* depth radix sort + tie fix               */
+    FDGS_STAGE_OFFSETS = 3,      /* instance offsets (scan)                  */
+    FDGS_STAGE_DUPLICATE = 4,    /* tile-key emission                        */
+    FDGS_STAGE_TILE_SORT = 5,    /* tile radix sort                          */
+    FDGS_STAGE_RANGES = 6,       /* tile ranges                              */
+    FDGS_STAGE_COMPOSITE = 7,    /* per-tile blending                        */
+    FDGS_STAGE_BWD_COMPOSITE = 8,
+    FDGS_STAGE_BWD_PREPROCESS = 9,
+    FDGS_NUM_STAGES = 10
+};
+typedef struct {
+    double ms[FDGS_NUM_STAGES];      /* summed event time per stage        */
+    int64_t calls[FDGS_NUM_STAGES];  /* times each stage ran               */
+    int64_t processed;               /* sums over the profiled forwards    */
+    int64_t visible;
+    int64_t instances;
+    uint64_t pairs;                  /* (pixel, Gaussian) evaluations      */
+} fdgs_profile;
+
+/* Turn profiling on (1) or off (0) for subsequent calls on this context. */
+FDGS_API fdgs_status fdgs_profile_enable(fdgs_ctx *ctx, int32_t enable);
+/* Read (and with reset=1 clear) the totals.  Synchronises the device. */
+FDGS_API fdgs_status fdgs_profile_read(fdgs_ctx *ctx, fdgs_profile *out, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDGS_H */

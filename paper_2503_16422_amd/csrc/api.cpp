@@ -1,0 +1,684 @@
+// C ABI of libfdgs: argument validation, scratch management and the order in
+// which the kernels of one render are enqueued.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fdgs_internal.h"
+
+using namespace fdgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+fdgs_status fail(fdgs_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(FDGS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+hipError_t ensure(Buf &b, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (bytes <= b.cap) return hipSuccess;
+    if (b.p) {
+        // kernels already enqueued may still use the old block
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    const size_t want = std::max(bytes, b.cap + b.cap / 2);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.cap = want;
+    return hipSuccess;
+}
+
+void release(Buf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+bool valid_tile(int w, int h) { return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8); }
+
+int bits_for(int64_t v) {   // bits needed to represent values in [0, v)
+    int b = 0;
+    while (b < 63 && (int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+}  // namespace
+
+struct fdgs_state {
+    fdgs_ctx *owner = nullptr;
+    bool has_forward = false;
+    // per processed Gaussian
+    Buf rec, depth_key, rect, tiles, visible, vis_pos, order_k, order_v, order_k2, order_v2, offsets;
+    // per instance
+    Buf tkeys, tids, tkeys2, tids2;
+    // per tile / pixel
+    Buf ranges, T_final, n_contrib;
+    Buf counts;        // int64[4]: n_vis, n_inst
+    Buf g2d;
+    Buf scratch;
+    // what the forward used
+    fdgs_model model{};
+    const uint32_t *idx = nullptr;
+    const int64_t *n_idx_dev = nullptr;
+    KCam cam{};
+    double t = 0.0;
+    RenderParams rp{};
+    int32_t batch = 128;
+    int64_t n_max = 0;
+    int64_t capacity = 0;
+    uint32_t *sorted_ids = nullptr;   // points into tids or tids2
+    uint32_t *sorted_keys = nullptr;
+    int32_t W = 0, H = 0;
+
+    void free_all() {
+        for (Buf *b : {&rec, &depth_key, &rect, &tiles, &visible, &vis_pos, &order_k, &order_v, &order_k2,
+                       &order_v2, &offsets, &tkeys, &tids, &tkeys2, &tids2, &ranges, &T_final,
+                       &n_contrib, &counts, &g2d, &scratch})
+            release(*b);
+    }
+};
+
+struct PendingStage {
+    int stage;
+    hipEvent_t e0, e1;
+};
+
+struct fdgs_ctx {
+    int32_t device = 0;
+    fdgs_state scratch_state;
+    std::vector<fdgs_state *> states;
+    Buf overflow;                  // int32 device flag
+    Buf mask_frames, mask_views, mask_scratch;
+    int64_t *host_counts = nullptr;  // pinned
+    // profiling
+    bool prof = false;
+    Buf prof_acc;                  // uint64[4]: processed, visible, instances, pairs
+    std::vector<hipEvent_t> free_events;
+    std::vector<PendingStage> pending;
+    double ms[FDGS_NUM_STAGES] = {};
+    int64_t calls[FDGS_NUM_STAGES] = {};
+
+    hipEvent_t get_event() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+namespace {
+
+// Records HIP events around one stage when profiling is on.
+struct StageTimer {
+    fdgs_ctx *c;
+    int stage;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr;
+    StageTimer(fdgs_ctx *c_, int stage_, hipStream_t s_) : c(c_), stage(stage_), s(s_) {
+        if (c->prof && (e0 = c->get_event())) (void)hipEventRecord(e0, s);
+    }
+    ~StageTimer() {
+        if (!c->prof || !e0) return;
+        hipEvent_t e1 = c->get_event();
+        if (!e1) return;
+        (void)hipEventRecord(e1, s);
+        c->pending.push_back(PendingStage{stage, e0, e1});
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *fdgs_last_error(void) { return g_err.c_str(); }
+
+const char *fdgs_version(void) { return "fdgs 0.1 (gfx950)"; }
+
+void fdgs_render_cfg_default(fdgs_render_cfg *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->tile_w = 16;
+    cfg->tile_h = 16;
+    cfg->batch = 128;
+    cfg->alpha_min = 1.0f / 255.0f;
+    cfg->alpha_max = 0.99f;
+    cfg->t_min = 1e-4f;
+    cfg->dilation = 0.3f;
+    cfg->temporal_cull = 1;
+    cfg->instance_capacity = 0;
+}
+
+fdgs_status fdgs_create(fdgs_ctx **out, int32_t device) {
+    if (!out) return fail(FDGS_ERR_INVALID_ARG, "fdgs_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(FDGS_ERR_INVALID_ARG, "fdgs_create: device %d not in [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    fdgs_ctx *c = new (std::nothrow) fdgs_ctx();
+    if (!c) return fail(FDGS_ERR_HIP, "fdgs_create: out of host memory");
+    c->device = device;
+    c->scratch_state.owner = c;
+    hipError_t e = ensure(c->overflow, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(c->overflow.p, 0, sizeof(int32_t));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_counts, 4 * sizeof(int64_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        release(c->overflow);
+        delete c;
+        return fail(FDGS_ERR_HIP, "fdgs_create: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
+    if (!ctx) return FDGS_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (fdgs_state *s : ctx->states) {
+        s->free_all();
+        delete s;
+    }
+    ctx->scratch_state.free_all();
+    release(ctx->overflow);
+    release(ctx->mask_frames);
+    release(ctx->mask_views);
+    release(ctx->mask_scratch);
+    release(ctx->prof_acc);
+    for (auto &p : ctx->pending) {
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
+    if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
+    delete ctx;
+    return FDGS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+fdgs_status check_model(const fdgs_model *m, const char *fn) {
+    if (!m) return fail(FDGS_ERR_INVALID_ARG, "%s: model is NULL", fn);
+    if (m->n < 0 || m->n >= (int64_t(1) << 31))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: model n=%lld out of range", fn, (long long)m->n);
+    if (m->sh_degree < 0 || m->sh_degree > 3)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: sh_degree %d not in 0..3", fn, m->sh_degree);
+    if (m->n > 0 && (!m->mean || !m->log_scale || !m->q_left || !m->q_right || !m->opacity_logit || !m->sh))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: a model pointer is NULL", fn);
+    return FDGS_OK;
+}
+
+fdgs_status check_camera(const fdgs_camera *c, const char *fn) {
+    if (!c) return fail(FDGS_ERR_INVALID_ARG, "%s: camera is NULL", fn);
+    if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: image %dx%d out of range", fn, c->width, c->height);
+    if (!(c->znear > 0.0) || !std::isfinite(c->znear))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: znear must be > 0", fn);
+    const double v[] = {c->fx, c->fy, c->cx, c->cy};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite intrinsics", fn);
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(c->R[k])) return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite R", fn);
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(c->tvec[k])) return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite tvec", fn);
+    if (!(c->fx > 0.0) || !(c->fy > 0.0)) return fail(FDGS_ERR_INVALID_ARG, "%s: focal must be > 0", fn);
+    return FDGS_OK;
+}
+
+fdgs_status check_cfg(const fdgs_render_cfg *cfg, const char *fn) {
+    if (!cfg) return fail(FDGS_ERR_INVALID_ARG, "%s: cfg is NULL", fn);
+    if (!valid_tile(cfg->tile_w, cfg->tile_h))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: tile %dx%d not one of 8x8, 16x16, 32x8", fn, cfg->tile_w,
+                    cfg->tile_h);
+    if (cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: batch %d not one of 64, 128, 256", fn, cfg->batch);
+    if (!(cfg->alpha_min > 0.0f) || !(cfg->alpha_max > cfg->alpha_min) || !(cfg->alpha_max < 1.0f))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: need 0 < alpha_min < alpha_max < 1", fn);
+    if (!(cfg->t_min > 0.0f) || !(cfg->t_min < 1.0f))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: need 0 < t_min < 1", fn);
+    if (!(cfg->dilation >= 0.0f) || !std::isfinite(cfg->dilation))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: dilation must be finite and >= 0", fn);
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(cfg->bg[k])) return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite bg", fn);
+    if (cfg->instance_capacity < 0 || cfg->instance_capacity > 0xffffffffll)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: instance_capacity out of range", fn);
+    return FDGS_OK;
+}
+
+KModel kmodel(const fdgs_model *m) {
+    return KModel{m->mean, m->log_scale, m->q_left, m->q_right, m->opacity_logit, m->sh, m->n, m->sh_degree};
+}
+
+KCam kcam(const fdgs_camera *c) {
+    KCam k;
+    std::memcpy(k.R, c->R, sizeof k.R);
+    std::memcpy(k.t, c->tvec, sizeof k.t);
+    k.fx = c->fx;
+    k.fy = c->fy;
+    k.cx = c->cx;
+    k.cy = c->cy;
+    k.znear = c->znear;
+    k.W = c->width;
+    k.H = c->height;
+    return k;
+}
+
+fdgs_state *find_state(fdgs_ctx *ctx, fdgs_state *s) {
+    for (fdgs_state *x : ctx->states)
+        if (x == s) return x;
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdgs_status fdgs_slice_4d(fdgs_ctx *ctx, const fdgs_model *model, double t, const uint32_t *idx, int64_t m,
+                          float *out_mean3, float *out_cov3, float *out_p, hipStream_t stream) {
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "fdgs_slice_4d: ctx is NULL");
+    if (fdgs_status st = check_model(model, "fdgs_slice_4d")) return st;
+    if (!std::isfinite(t)) return fail(FDGS_ERR_INVALID_ARG, "fdgs_slice_4d: t is not finite");
+    if (m < 0 || m >= (int64_t(1) << 31)) return fail(FDGS_ERR_INVALID_ARG, "fdgs_slice_4d: m out of range");
+    if (!idx && m > model->n) return fail(FDGS_ERR_INVALID_ARG, "fdgs_slice_4d: m > n without idx");
+    if (m > 0 && (!out_mean3 || !out_cov3 || !out_p))
+        return fail(FDGS_ERR_INVALID_ARG, "fdgs_slice_4d: an output pointer is NULL");
+    if (m > 0 && idx && model->n == 0) return fail(FDGS_ERR_INVALID_ARG, "fdgs_slice_4d: idx into empty model");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_slice(kmodel(model), t, idx, m, out_mean3, out_cov3, out_p, stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const fdgs_mask_spec *spec,
+                                   uint32_t *out_bits, uint32_t *out_idx, int64_t *out_count,
+                                   hipStream_t stream) {
+    const char *fn = "fdgs_build_active_mask";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (fdgs_status st = check_model(model, fn)) return st;
+    if (!spec) return fail(FDGS_ERR_INVALID_ARG, "%s: spec is NULL", fn);
+    if (spec->mode != FDGS_MASK_TEMPORAL && spec->mode != FDGS_MASK_TEMPORAL_AND_TILE)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: unknown mode %d", fn, spec->mode);
+    if (spec->n_frames < 1 || spec->n_frames > 256 || !spec->frame_times)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: need 1..256 frame times", fn);
+    for (int f = 0; f < spec->n_frames; ++f)
+        if (!std::isfinite(spec->frame_times[f])) return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite frame time", fn);
+    if (spec->mode == FDGS_MASK_TEMPORAL_AND_TILE) {
+        if (spec->n_views < 1 || spec->n_views > 64 || !spec->views)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: tile mode needs 1..64 views", fn);
+        for (int v = 0; v < spec->n_views; ++v)
+            if (fdgs_status st = check_camera(&spec->views[v], fn)) return st;
+        if (!std::isfinite(spec->key_lo) || !std::isfinite(spec->key_hi))
+            return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite keyframe time", fn);
+    }
+    if (!out_bits || !out_idx || !out_count) return fail(FDGS_ERR_INVALID_ARG, "%s: an output is NULL", fn);
+    const float amin = spec->alpha_min > 0.0f ? spec->alpha_min : 1.0f / 255.0f;
+    if (!(amin < 1.0f)) return fail(FDGS_ERR_INVALID_ARG, "%s: alpha_min must be < 1", fn);
+    const float dil = spec->dilation >= 0.0f ? spec->dilation : 0.3f;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t n = model->n;
+    HIP_TRY(ensure(ctx->mask_frames, sizeof(double) * spec->n_frames));
+    HIP_TRY(hipMemcpyAsync(ctx->mask_frames.p, spec->frame_times, sizeof(double) * spec->n_frames,
+                           hipMemcpyHostToDevice, stream));
+    std::vector<KCam> views;
+    if (spec->mode == FDGS_MASK_TEMPORAL_AND_TILE) {
+        for (int v = 0; v < spec->n_views; ++v) views.push_back(kcam(&spec->views[v]));
+        HIP_TRY(ensure(ctx->mask_views, sizeof(KCam) * views.size()));
+        HIP_TRY(hipMemcpyAsync(ctx->mask_views.p, views.data(), sizeof(KCam) * views.size(),
+                               hipMemcpyHostToDevice, stream));
+    }
+    MaskArgs a;
+    a.frames = ctx->mask_frames.as<double>();
+    a.n_frames = spec->n_frames;
+    a.views = ctx->mask_views.as<KCam>();
+    a.n_views = spec->mode == FDGS_MASK_TEMPORAL_AND_TILE ? spec->n_views : 0;
+    a.key_lo = spec->key_lo;
+    a.key_hi = spec->key_hi;
+    a.mode = spec->mode;
+    a.level = 2.0 * std::log(1.0 / (double)amin);
+    a.rect_level = a.level * (1.0 + 1e-4) + 1e-4;
+    a.dilation = dil;
+    HIP_TRY(launch_mask_bits(kmodel(model), a, out_bits, stream));
+    HIP_TRY(ensure(ctx->mask_scratch, compact_scratch_bytes(n)));
+    HIP_TRY(compact_bits(out_bits, n, out_idx, out_count, ctx->mask_scratch.p, stream));
+    // the host arrays were copied asynchronously: finish before returning
+    HIP_TRY(hipStreamSynchronize(stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_render_forward(fdgs_ctx *ctx, const fdgs_model *model, const uint32_t *idx,
+                                const int64_t *n_idx_dev, const fdgs_camera *cam, double t,
+                                const fdgs_render_cfg *cfg, float *out_rgb, float *out_T,
+                                fdgs_state **keep_state, hipStream_t stream) {
+    const char *fn = "fdgs_render_forward";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (fdgs_status st = check_model(model, fn)) return st;
+    if (fdgs_status st = check_camera(cam, fn)) return st;
+    if (fdgs_status st = check_cfg(cfg, fn)) return st;
+    if (!std::isfinite(t)) return fail(FDGS_ERR_INVALID_ARG, "%s: t is not finite", fn);
+    if (idx && !n_idx_dev) return fail(FDGS_ERR_INVALID_ARG, "%s: idx given without n_idx_dev", fn);
+    if (!out_rgb) return fail(FDGS_ERR_INVALID_ARG, "%s: out_rgb is NULL", fn);
+    fdgs_state *S = &ctx->scratch_state;
+    if (keep_state) {
+        if (*keep_state) {
+            S = find_state(ctx, *keep_state);
+            if (!S) return fail(FDGS_ERR_STATE, "%s: *keep_state does not belong to this context", fn);
+        } else {
+            S = new (std::nothrow) fdgs_state();
+            if (!S) return fail(FDGS_ERR_HIP, "%s: out of host memory", fn);
+            S->owner = ctx;
+            ctx->states.push_back(S);
+            *keep_state = S;
+        }
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    S->has_forward = false;
+    const int32_t W = cam->width, H = cam->height;
+    RenderParams rp;
+    rp.tile_w = cfg->tile_w;
+    rp.tile_h = cfg->tile_h;
+    rp.tiles_x = (W + cfg->tile_w - 1) / cfg->tile_w;
+    rp.tiles_y = (H + cfg->tile_h - 1) / cfg->tile_h;
+    for (int k = 0; k < 3; ++k) rp.bg[k] = cfg->bg[k];
+    rp.alpha_min = cfg->alpha_min;
+    rp.alpha_max = cfg->alpha_max;
+    rp.t_min = cfg->t_min;
+    rp.dilation = cfg->dilation;
+    rp.temporal_cull = cfg->temporal_cull ? 1 : 0;
+    const int32_t n_tiles = rp.tiles_x * rp.tiles_y;
+    const int64_t n_max = model->n;
+    const int64_t *n_proc_dev = idx ? n_idx_dev : nullptr;
+    const KModel km = kmodel(model);
+    const KCam kc = kcam(cam);
+    const int64_t npx = (int64_t)W * H;
+
+    // per processed Gaussian buffers
+    HIP_TRY(ensure(S->rec, sizeof(Rec2D) * n_max));
+    HIP_TRY(ensure(S->depth_key, sizeof(uint64_t) * n_max));
+    HIP_TRY(ensure(S->rect, sizeof(int32_t) * 4 * n_max));
+    HIP_TRY(ensure(S->tiles, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->visible, n_max));
+    HIP_TRY(ensure(S->vis_pos, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_k, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_v, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_k2, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_v2, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->offsets, sizeof(uint64_t) * n_max));
+    HIP_TRY(ensure(S->counts, sizeof(int64_t) * 4));
+    HIP_TRY(ensure(S->ranges, sizeof(uint32_t) * 2 * n_tiles));
+    HIP_TRY(ensure(S->T_final, sizeof(float) * npx));
+    HIP_TRY(ensure(S->n_contrib, sizeof(uint32_t) * npx));
+    size_t scratch = std::max(scan_scratch_bytes(n_max), sort_scratch_bytes(n_max));
+    HIP_TRY(ensure(S->scratch, scratch));
+    int64_t *counts = S->counts.as<int64_t>();
+
+    PreprocOut po{S->rec.as<Rec2D>(), S->depth_key.as<uint64_t>(), S->rect.as<int32_t>(),
+                  S->tiles.as<uint32_t>(), S->visible.as<uint8_t>()};
+    {
+        StageTimer tm(ctx, FDGS_STAGE_PREPROCESS, stream);
+        HIP_TRY(launch_preprocess(km, idx, n_proc_dev, n_max, kc, t, rp, po, stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_COMPACT, stream);
+        HIP_TRY(scan_flags_u8(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(), n_proc_dev, n_max,
+                              counts + 0, S->scratch.p, stream));
+        HIP_TRY(launch_scatter_visible(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(),
+                                       S->depth_key.as<uint64_t>(), n_proc_dev, n_max, S->order_k.as<uint32_t>(),
+                                       S->order_v.as<uint32_t>(), stream));
+    }
+    int alt = 0;
+    uint32_t *ov = nullptr;
+    {
+        StageTimer tm(ctx, FDGS_STAGE_DEPTH_SORT, stream);
+        HIP_TRY(radix_sort_u32(S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->order_k2.as<uint32_t>(),
+                               S->order_v2.as<uint32_t>(), counts + 0, n_max, 0, 32, S->scratch.p, &alt, stream));
+        uint32_t *ok = alt ? S->order_k2.as<uint32_t>() : S->order_k.as<uint32_t>();
+        ov = alt ? S->order_v2.as<uint32_t>() : S->order_v.as<uint32_t>();
+        HIP_TRY(launch_fix_depth_ties(ok, ov, S->depth_key.as<uint64_t>(), counts + 0, n_max,
+                                      ctx->overflow.as<int32_t>(), stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_OFFSETS, stream);
+        HIP_TRY(scan_u32_to_u64(S->tiles.as<uint32_t>(), ov, S->offsets.as<uint64_t>(), counts + 0, n_max,
+                                counts + 1, S->scratch.p, stream));
+    }
+
+    int64_t capacity = cfg->instance_capacity;
+    if (capacity == 0) {
+        HIP_TRY(hipMemcpyAsync(ctx->host_counts, counts, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        capacity = ctx->host_counts[1];
+        if (capacity > 0xffffffffll)
+            return fail(FDGS_ERR_CAPACITY, "%s: %lld tile instances exceed 2^32", fn, (long long)capacity);
+    }
+    HIP_TRY(ensure(S->tkeys, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->tids, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->tkeys2, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->tids2, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->scratch, std::max(scratch, sort_scratch_bytes(capacity))));
+    {
+        StageTimer tm(ctx, FDGS_STAGE_DUPLICATE, stream);
+        HIP_TRY(launch_duplicate(ov, S->offsets.as<uint64_t>(), S->rect.as<int32_t>(), counts + 0, n_max, rp,
+                                 S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), counts + 1, capacity,
+                                 ctx->overflow.as<int32_t>(), stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_TILE_SORT, stream);
+        int alt2 = 0;
+        HIP_TRY(radix_sort_u32(S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), S->tkeys2.as<uint32_t>(),
+                               S->tids2.as<uint32_t>(), counts + 1, capacity, 0, std::max(1, bits_for(n_tiles)),
+                               S->scratch.p, &alt2, stream));
+        S->sorted_keys = alt2 ? S->tkeys2.as<uint32_t>() : S->tkeys.as<uint32_t>();
+        S->sorted_ids = alt2 ? S->tids2.as<uint32_t>() : S->tids.as<uint32_t>();
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_RANGES, stream);
+        HIP_TRY(launch_tile_ranges(S->sorted_keys, counts + 1, capacity, n_tiles, S->ranges.as<uint32_t>(), stream));
+    }
+    const bool need_state = keep_state != nullptr;
+    float *T_out = need_state ? S->T_final.as<float>() : out_T;
+    uint64_t *acc = nullptr;
+    if (ctx->prof) {
+        HIP_TRY(ensure(ctx->prof_acc, 4 * sizeof(uint64_t)));
+        acc = ctx->prof_acc.as<uint64_t>();
+        HIP_TRY(launch_accumulate_counts(n_proc_dev, n_max, counts, capacity, acc, stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_COMPOSITE, stream);
+        HIP_TRY(launch_composite(rp, W, H, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
+                                 out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
+                                 acc ? acc + 3 : nullptr, stream));
+    }
+    if (need_state && out_T)
+        HIP_TRY(hipMemcpyAsync(out_T, S->T_final.p, sizeof(float) * npx, hipMemcpyDeviceToDevice, stream));
+
+    S->model = *model;
+    S->idx = idx;
+    S->n_idx_dev = n_idx_dev;
+    S->cam = kc;
+    S->t = t;
+    S->rp = rp;
+    S->batch = cfg->batch;
+    S->n_max = n_max;
+    S->capacity = capacity;
+    S->W = W;
+    S->H = H;
+    S->has_forward = true;
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *dL_drgb, const fdgs_grads *grads,
+                                 hipStream_t stream) {
+    const char *fn = "fdgs_render_backward";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    fdgs_state *S = state ? find_state(ctx, state) : nullptr;
+    if (!S) return fail(FDGS_ERR_STATE, "%s: state is not a live state of this context", fn);
+    if (!S->has_forward) return fail(FDGS_ERR_STATE, "%s: state holds no forward pass", fn);
+    if (!dL_drgb || !grads) return fail(FDGS_ERR_INVALID_ARG, "%s: dL_drgb or grads is NULL", fn);
+    if (S->model.n > 0 && (!grads->mean || !grads->log_scale || !grads->q_left || !grads->q_right ||
+                           !grads->opacity_logit || !grads->sh))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: a gradient pointer is NULL", fn);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(ensure(S->g2d, sizeof(float) * 9 * std::max<int64_t>(S->n_max, 1)));
+    {
+        StageTimer tm(ctx, FDGS_STAGE_BWD_COMPOSITE, stream);
+        HIP_TRY(launch_fill_u32(S->g2d.as<uint32_t>(), 9 * std::max<int64_t>(S->n_max, 1), 0u, stream));
+        HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ranges.as<uint32_t>(), S->sorted_ids,
+                                          S->rec.as<Rec2D>(), S->T_final.as<float>(), S->n_contrib.as<uint32_t>(),
+                                          dL_drgb, S->g2d.as<float>(), S->n_max, stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_BWD_PREPROCESS, stream);
+        const int64_t *n_proc_dev = S->idx ? S->n_idx_dev : nullptr;
+        HIP_TRY(launch_preprocess_backward(kmodel(&S->model), S->idx, n_proc_dev, S->n_max, S->cam, S->t, S->rp,
+                                           S->visible.as<uint8_t>(), S->g2d.as<float>(), *grads, stream));
+    }
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_state_release(fdgs_ctx *ctx, fdgs_state *state) {
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "fdgs_state_release: ctx is NULL");
+    if (!state) return FDGS_OK;
+    auto it = std::find(ctx->states.begin(), ctx->states.end(), state);
+    if (it == ctx->states.end()) return fail(FDGS_ERR_STATE, "fdgs_state_release: unknown state");
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    state->free_all();
+    delete state;
+    ctx->states.erase(it);
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_state_binning(fdgs_ctx *ctx, fdgs_state *state, fdgs_binning *out, hipStream_t stream) {
+    const char *fn = "fdgs_state_binning";
+    if (!ctx || !out) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx or out is NULL", fn);
+    fdgs_state *S = state ? find_state(ctx, state) : nullptr;
+    if (!S || !S->has_forward) return fail(FDGS_ERR_STATE, "%s: no forward pass in state", fn);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipMemcpyAsync(ctx->host_counts, S->counts.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    int64_t nproc = S->n_max;
+    if (S->idx) HIP_TRY(hipMemcpyAsync(ctx->host_counts + 2, S->n_idx_dev, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (S->idx) nproc = std::min(ctx->host_counts[2], S->n_max);
+    out->sorted_ids = S->sorted_ids;
+    out->tile_ranges = S->ranges.as<uint32_t>();
+    out->rects = S->rect.as<int32_t>();
+    out->depth = reinterpret_cast<const double *>(S->depth_key.p);
+    out->visible = S->visible.as<uint8_t>();
+    out->n_vis = ctx->host_counts[0];
+    out->n_inst = std::min(ctx->host_counts[1], S->capacity);
+    out->n_proc = nproc;
+    out->n_tiles = S->rp.tiles_x * S->rp.tiles_y;
+    out->tiles_x = S->rp.tiles_x;
+    out->tiles_y = S->rp.tiles_y;
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_profile_enable(fdgs_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "fdgs_profile_enable: ctx is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (enable && !ctx->prof_acc.p) {
+        HIP_TRY(ensure(ctx->prof_acc, 4 * sizeof(uint64_t)));
+        HIP_TRY(hipMemset(ctx->prof_acc.p, 0, 4 * sizeof(uint64_t)));
+    }
+    ctx->prof = enable != 0;
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_profile_read(fdgs_ctx *ctx, fdgs_profile *out, int32_t reset) {
+    if (!ctx || !out) return fail(FDGS_ERR_INVALID_ARG, "fdgs_profile_read: ctx or out is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    for (auto &p : ctx->pending) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.e0, p.e1));
+        ctx->ms[p.stage] += ms;
+        ctx->calls[p.stage] += 1;
+        ctx->free_events.push_back(p.e0);
+        ctx->free_events.push_back(p.e1);
+    }
+    ctx->pending.clear();
+    std::memset(out, 0, sizeof *out);
+    for (int k = 0; k < FDGS_NUM_STAGES; ++k) {
+        out->ms[k] = ctx->ms[k];
+        out->calls[k] = ctx->calls[k];
+    }
+    if (ctx->prof_acc.p) {
+        uint64_t acc[4];
+        HIP_TRY(hipMemcpy(acc, ctx->prof_acc.p, sizeof acc, hipMemcpyDeviceToHost));
+        out->processed = (int64_t)acc[0];
+        out->visible = (int64_t)acc[1];
+        out->instances = (int64_t)acc[2];
+        out->pairs = acc[3];
+        if (reset) HIP_TRY(hipMemset(ctx->prof_acc.p, 0, sizeof acc));
+    }
+    if (reset) {
+        for (int k = 0; k < FDGS_NUM_STAGES; ++k) {
+            ctx->ms[k] = 0.0;
+            ctx->calls[k] = 0;
+        }
+    }
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_check_overflow(fdgs_ctx *ctx, hipStream_t stream) {
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "fdgs_check_overflow: ctx is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    int32_t flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, ctx->overflow.p, sizeof flag, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (flag) {
+        HIP_TRY(hipMemsetAsync(ctx->overflow.p, 0, sizeof flag, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (flag & 1)
+            return fail(FDGS_ERR_CAPACITY, "fdgs_check_overflow: a forward pass exceeded its instance capacity");
+        return fail(FDGS_ERR_UNSUPPORTED,
+                    "fdgs_check_overflow: more than 4096 Gaussians shared one float32 depth; "
+                    "their order fell back to processing order");
+    }
+    return FDGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Device helpers shared by the integer kernels: wave64 and block scans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdgs {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+// Inclusive sum over the 64 lanes of a wavefront.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Exclusive sum over a block of NT threads (NT a multiple of 64, <= 1024).
+// `tmp` must hold NT/64 + 1 elements of shared memory.  Returns the thread's
+// exclusive prefix; *total receives the block total.  Contains barriers.
+template <int NT, typename T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T *tmp, T *total) {
+    constexpr int NW = NT / 64;
+    const T inc = wave_inclusive_sum(v);
+    if (lane_id() == 63) tmp[wave_id()] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int w = 0; w < NW; ++w) {
+            const T x = tmp[w];
+            tmp[w] = run;
+            run += x;
+        }
+        tmp[NW] = run;
+    }
+    __syncthreads();
+    const T res = tmp[wave_id()] + inc - v;
+    *total = tmp[NW];
+    __syncthreads();
+    return res;
+}
+
+}  // namespace fdgs

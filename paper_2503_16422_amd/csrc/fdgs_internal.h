@@ -1,0 +1,122 @@
+// Internal declarations shared by the host side of libfdgs (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fdgs.h"
+
+namespace fdgs {
+
+// Camera as passed to kernels (by value).
+struct KCam {
+    double R[9];
+    double t[3];
+    double fx, fy, cx, cy, znear;
+    int32_t W, H;
+};
+
+// Model pointers as passed to kernels.
+struct KModel {
+    const float *mean, *log_scale, *q_left, *q_right, *logit, *sh;
+    int64_t n;
+    int32_t sh_degree;
+};
+
+// Per visible Gaussian record consumed by the compositor (48 B, 16-B aligned).
+//   a: u_hi, v_hi, u_lo, v_lo    (pixel-space centre as a float pair)
+//   b: conic a, b, c, opacity    (Sigma_2D^{-1} = [[a, b], [b, c]]; sigma * p(t))
+//   c: r, g, b, depth (float32)
+struct alignas(16) Rec2D {
+    float4 a, b, c;
+};
+
+struct RenderParams {
+    int32_t tile_w, tile_h, tiles_x, tiles_y;
+    float bg[3];
+    float alpha_min, alpha_max, t_min, dilation;
+    int32_t temporal_cull;
+};
+
+// Launch wrappers (each .hip file owns its kernels).  All are asynchronous.
+hipError_t launch_slice(const KModel &m, double t, const uint32_t *idx, int64_t count,
+                        float *mean3, float *cov3, float *p, hipStream_t s);
+
+struct PreprocOut {
+    Rec2D *rec;          // [P]
+    uint64_t *depth_key; // [P] float64 bits of z
+    int32_t *rect;       // [P][4]
+    uint32_t *tiles;     // [P] tiles touched (0 = not visible)
+    uint8_t *visible;    // [P]
+};
+hipError_t launch_preprocess(const KModel &m, const uint32_t *idx, const int64_t *n_dev,
+                             int64_t n_max, const KCam &cam, double t, const RenderParams &rp,
+                             const PreprocOut &out, hipStream_t s);
+
+struct MaskArgs {
+    const double *frames;   // device [n_frames]
+    int32_t n_frames;
+    const KCam *views;      // device [n_views]
+    int32_t n_views;
+    double key_lo, key_hi;
+    int32_t mode;
+    double level;           // 2 ln(1/alpha_min)
+    double rect_level;      // footprint Mahalanobis level incl. margin
+    double dilation;
+};
+hipError_t launch_mask_bits(const KModel &m, const MaskArgs &a, uint32_t *bits, hipStream_t s);
+
+// Exclusive scans.  n is read from n_dev when non-null (bounded by n_max).
+size_t scan_scratch_bytes(int64_t n_max);
+hipError_t scan_flags_u8(const uint8_t *in, uint32_t *out, const int64_t *n_dev, int64_t n_max,
+                         int64_t *total, void *scratch, hipStream_t s);
+hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t *out,
+                           const int64_t *n_dev, int64_t n_max, int64_t *total,
+                           void *scratch, hipStream_t s);
+hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t *count,
+                        void *scratch, hipStream_t s);
+size_t compact_scratch_bytes(int64_t n);
+
+// Stable LSD radix sort of (key, uint32 value) pairs, 8-bit digits.
+size_t sort_scratch_bytes(int64_t n_max);
+hipError_t radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                          const int64_t *n_dev, int64_t n_max, int begin_bit, int end_bit,
+                          void *scratch, int *result_in_alt, hipStream_t s);
+
+// Visible-set compaction, depth ordering and tile binning.
+hipError_t launch_scatter_visible(const uint8_t *visible, const uint32_t *pos,
+                                  const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
+                                  uint32_t *keys32, uint32_t *vals, hipStream_t s);
+// flag |= 2 when a run of equal float32 depths is too long to reorder.
+hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_t *depth_key,
+                                 const int64_t *n_vis_dev, int64_t n_max, int32_t *flag, hipStream_t s);
+hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
+                            const int64_t *n_vis_dev, int64_t n_max, const RenderParams &rp,
+                            uint32_t *tile_keys, uint32_t *ids, const int64_t *n_inst_dev,
+                            int64_t capacity, int32_t *overflow, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
+                              int32_t n_tiles, uint32_t *ranges, hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+// Profiling: acc[0..2] += processed, visible, instances (instances clamped to capacity).
+hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
+                                    int64_t capacity, uint64_t *acc, hipStream_t s);
+
+// Compositing.  pair_counter (optional) accumulates evaluated (pixel, Gaussian) pairs.
+hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                            float *out_rgb, float *out_T, uint32_t *n_contrib,
+                            uint64_t *pair_counter, hipStream_t s);
+
+// Backward.
+hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+                                     const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                                     const float *T_final, const uint32_t *n_contrib,
+                                     const float *dL_drgb, float *g2d, int64_t n_proc_max,
+                                     hipStream_t s);
+hipError_t launch_preprocess_backward(const KModel &m, const uint32_t *idx, const int64_t *n_dev,
+                                      int64_t n_max, const KCam &cam, double t,
+                                      const RenderParams &rp, const uint8_t *visible,
+                                      const float *g2d, const fdgs_grads &grads, hipStream_t s);
+
+}  // namespace fdgs

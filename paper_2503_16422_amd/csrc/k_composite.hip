@@ -1,0 +1,311 @@
+// Per-tile front-to-back compositing (Eq. 2 with alpha from Eq. 3) and its
+// adjoint.
+//
+// One workgroup per screen tile, one pixel per thread.  The tile's depth-ordered
+// list is walked in batches: the workgroup stages a batch of records in LDS
+// (centre relative to the tile origin, pre-scaled conic, opacity, colour), then
+// every pixel evaluates the batch.  A pixel stops before the Gaussian that would
+// take its transmittance below t_min; the workgroup leaves the list as soon as
+// every pixel has stopped.  No MFMA: per (pixel, Gaussian) pair the work is an
+// exponential and a dozen FMAs, not a contraction.
+//
+// Precision: the centre is stored as a float pair (hi + lo) and re-centred on
+// the tile while staging, so the per-pair offset dx = px + 0.5 - u is exact to
+// ~1e-6 px even at the right edge of a 1352-px image.
+#include <hip/hip_runtime.h>
+
+#include "dev_util.h"
+#include "fdgs_internal.h"
+
+namespace fdgs {
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.69314718055994531f;
+
+// Staged form of a record's conic: base-2 exponent coefficients, so that
+// G = exp(-1/2 d^T conic d) = exp2(ka dx^2 + kb dx dy + kc dy^2).
+__device__ __forceinline__ float4 staged_conic(const Rec2D &r) {
+    return make_float4(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y, -0.5f * kLog2e * r.b.z, r.b.w);
+}
+
+// Base-2 exponent of the 2D Gaussian at offset (dx, dy).  Forward and adjoint
+// call this same function so that both take identical alpha decisions.
+__device__ __forceinline__ float gauss_exp2(float4 q, float dx, float dy) {
+    return fmaf(dx, fmaf(q.x, dx, q.y * dy), (q.z * dy) * dy);
+}
+
+struct CompArgs {
+    RenderParams rp;
+    int32_t W, H;
+    const uint32_t *ranges;
+    const uint32_t *ids;
+    const Rec2D *rec;
+    float *out_rgb;
+    float *out_T;
+    uint32_t *n_contrib;
+    unsigned long long *pairs;   // optional counter of evaluated pairs
+};
+
+template <int TW, int TH, int BATCH>
+__global__ void __launch_bounds__(TW *TH) composite_kernel(CompArgs a) {
+    constexpr int NT = TW * TH;
+    __shared__ float2 s_xy[BATCH];
+    __shared__ float4 s_cn[BATCH];    // base-2 exponent coefficients, opacity
+    __shared__ float4 s_rgb[BATCH];
+    const int tile = blockIdx.x;
+    const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int px = tx * TW + lx, py = ty * TH + ly;
+    const bool inside = px < a.W && py < a.H;
+    const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
+    const float ox = (float)(tx * TW), oy = (float)(ty * TH);
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const float amin = a.rp.alpha_min, amax = a.rp.alpha_max, tmin = a.rp.t_min;
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    uint32_t last = 0, evaluated = 0;
+    bool done = !inside;
+    for (uint32_t base = start; base < end; base += BATCH) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int cnt = (int)min((uint32_t)BATCH, end - base);
+        for (int k = threadIdx.x; k < cnt; k += NT) {
+            const Rec2D r = a.rec[a.ids[base + k]];
+            s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
+            s_cn[k] = staged_conic(r);
+            s_rgb[k] = r.c;
+        }
+        __syncthreads();
+        if (!done) {
+            int k = 0;
+            for (; k < cnt; ++k) {
+                const float2 c = s_xy[k];
+                const float4 q = s_cn[k];
+                const float dx = fx - c.x, dy = fy - c.y;
+                const float alpha = fminf(amax, q.w * __builtin_amdgcn_exp2f(gauss_exp2(q, dx, dy)));
+                if (alpha < amin) continue;
+                const float test = T * (1.0f - alpha);
+                if (test < tmin) {
+                    done = true;
+                    break;
+                }
+                const float w = alpha * T;
+                const float4 col = s_rgb[k];
+                C0 += col.x * w;
+                C1 += col.y * w;
+                C2 += col.z * w;
+                T = test;
+                last = base + k - start + 1;
+            }
+            evaluated += (uint32_t)min(k + 1, cnt);
+        }
+    }
+    if (a.pairs) {
+        const unsigned long long w = wave_sum((unsigned long long)evaluated);
+        if (lane_id() == 0) atomicAdd(a.pairs, w);
+    }
+    if (inside) {
+        const int64_t pix = (int64_t)py * a.W + px;
+        const int64_t plane = (int64_t)a.W * a.H;
+        a.out_rgb[pix] = C0 + T * a.rp.bg[0];
+        a.out_rgb[plane + pix] = C1 + T * a.rp.bg[1];
+        a.out_rgb[2 * plane + pix] = C2 + T * a.rp.bg[2];
+        if (a.out_T) a.out_T[pix] = T;
+        if (a.n_contrib) a.n_contrib[pix] = last;
+    }
+}
+
+struct BwdArgs {
+    RenderParams rp;
+    int32_t W, H;
+    const uint32_t *ranges;
+    const uint32_t *ids;
+    const Rec2D *rec;
+    const float *T_final;
+    const uint32_t *n_contrib;
+    const float *dL;
+    float *g2d;        // [n_proc][9]: du, dv, d conic a, b, c, d opacity, d rgb
+};
+
+// Adjoint, walking each pixel's list back to front from its last contributor.
+// The transmittance in front of Gaussian i is recovered as T_{i+1} / (1 - a_i)
+// from the stored final T, so no per-pixel list is kept.  With g = dL/dC and
+// S the colour accumulated behind i (absolute weights):
+//   dL/dc_i = a_i T_i g
+//   dL/da_i = T_i c_i.g - (S.g + T_final bg.g) / (1 - a_i)
+// then a_i = min(a_max, o_i G_i) -> (o_i, conic, centre).  Per-Gaussian sums
+// are reduced across the wavefront before one atomic add per value.
+template <int TW, int TH, int BATCH>
+__global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
+    constexpr int NT = TW * TH;
+    __shared__ float2 s_xy[BATCH];
+    __shared__ float4 s_cn[BATCH];    // staged conic and opacity, as in the forward
+    __shared__ float4 s_rgb[BATCH];
+    __shared__ uint32_t s_id[BATCH];
+    const int tile = blockIdx.x;
+    const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int px = tx * TW + lx, py = ty * TH + ly;
+    const bool inside = px < a.W && py < a.H;
+    const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
+    const float ox = (float)(tx * TW), oy = (float)(ty * TH);
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const float amin = a.rp.alpha_min, amax = a.rp.alpha_max;
+    const int64_t pix = (int64_t)py * a.W + px;
+    const int64_t plane = (int64_t)a.W * a.H;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, T = 1.f;
+    uint32_t last = 0;
+    if (inside) {
+        g0 = a.dL[pix];
+        g1 = a.dL[plane + pix];
+        g2 = a.dL[2 * plane + pix];
+        T = a.T_final[pix];
+        last = a.n_contrib[pix];
+    }
+    const float bgdot = T * (a.rp.bg[0] * g0 + a.rp.bg[1] * g1 + a.rp.bg[2] * g2);   // T_final bg.g
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+    // block-wide maximum of `last` bounds the walk
+    __shared__ uint32_t s_max;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    atomicMax(&s_max, last);
+    __syncthreads();
+    const uint32_t walk_end = start + s_max;
+    const int lane = lane_id();
+    for (int64_t top = (int64_t)walk_end; top > (int64_t)start; top -= BATCH) {
+        const uint32_t lo = (uint32_t)max((int64_t)start, top - BATCH);
+        const int cnt = (int)(top - lo);
+        __syncthreads();
+        for (int k = threadIdx.x; k < cnt; k += NT) {
+            const uint32_t id = a.ids[lo + k];
+            const Rec2D r = a.rec[id];
+            s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
+            s_cn[k] = staged_conic(r);
+            s_rgb[k] = r.c;
+            s_id[k] = id;
+        }
+        __syncthreads();
+        for (int k = cnt - 1; k >= 0; --k) {
+            const uint32_t pos = lo + k - start;   // position in the tile list
+            float du = 0.f, dv = 0.f, da = 0.f, db = 0.f, dc = 0.f, dop = 0.f;
+            float dr = 0.f, dg = 0.f, dbl = 0.f;
+            bool hit = false;
+            if (inside && pos < last) {
+                const float2 c = s_xy[k];
+                const float4 q = s_cn[k];
+                const float dx = fx - c.x, dy = fy - c.y;
+                const float G = __builtin_amdgcn_exp2f(gauss_exp2(q, dx, dy));
+                const float raw = q.w * G;
+                const float alpha = fminf(amax, raw);
+                if (alpha >= amin) {
+                    hit = true;
+                    const float4 col = s_rgb[k];
+                    T = T / (1.0f - alpha);               // transmittance in front of i
+                    const float w = alpha * T;
+                    dr = w * g0;
+                    dg = w * g1;
+                    dbl = w * g2;
+                    const float cg = col.x * g0 + col.y * g1 + col.z * g2;
+                    const float sg = S0 * g0 + S1 * g1 + S2 * g2;
+                    const float dalpha = T * cg - (sg + bgdot) / (1.0f - alpha);
+                    S0 += col.x * w;
+                    S1 += col.y * w;
+                    S2 += col.z * w;
+                    if (raw < amax) {
+                        // power = -1/2 (a dx^2 + 2 b dx dy + c dy^2) = ln2 * exponent
+                        dop = G * dalpha;
+                        const float dpow = alpha * dalpha;   // d alpha / d power
+                        da = -0.5f * dx * dx * dpow;
+                        db = -dx * dy * dpow;
+                        dc = -0.5f * dy * dy * dpow;
+                        du = -kLn2 * (2.0f * q.x * dx + q.y * dy) * dpow;   // = (a dx + b dy) dpow
+                        dv = -kLn2 * (q.y * dx + 2.0f * q.z * dy) * dpow;   // = (b dx + c dy) dpow
+                    }
+                }
+            }
+            if (__ballot(hit) != 0ull) {
+                du = wave_sum(du);
+                dv = wave_sum(dv);
+                da = wave_sum(da);
+                db = wave_sum(db);
+                dc = wave_sum(dc);
+                dop = wave_sum(dop);
+                dr = wave_sum(dr);
+                dg = wave_sum(dg);
+                dbl = wave_sum(dbl);
+                if (lane == 0) {
+                    float *o = a.g2d + (int64_t)s_id[k] * 9;
+                    atomicAdd(o + 0, du);
+                    atomicAdd(o + 1, dv);
+                    atomicAdd(o + 2, da);
+                    atomicAdd(o + 3, db);
+                    atomicAdd(o + 4, dc);
+                    atomicAdd(o + 5, dop);
+                    atomicAdd(o + 6, dr);
+                    atomicAdd(o + 7, dg);
+                    atomicAdd(o + 8, dbl);
+                }
+            }
+        }
+    }
+}
+
+template <int TW, int TH, int BATCH>
+void launch_fwd(const CompArgs &a, int n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, s, a);
+}
+
+template <int TW, int TH, int BATCH>
+void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, s, a);
+}
+
+}  // namespace
+
+#define FDGS_DISPATCH(LAUNCH, ARGS)                                                             \
+    do {                                                                                        \
+        const int key = rp.tile_w * 1000 + rp.tile_h;                                           \
+        bool ok = true;                                                                         \
+        if (key == 8008) {                                                                      \
+            if (batch == 64) LAUNCH<8, 8, 64>(ARGS, n_tiles, s);                                \
+            else if (batch == 128) LAUNCH<8, 8, 128>(ARGS, n_tiles, s);                         \
+            else if (batch == 256) LAUNCH<8, 8, 256>(ARGS, n_tiles, s);                         \
+            else ok = false;                                                                    \
+        } else if (key == 16016) {                                                              \
+            if (batch == 64) LAUNCH<16, 16, 64>(ARGS, n_tiles, s);                              \
+            else if (batch == 128) LAUNCH<16, 16, 128>(ARGS, n_tiles, s);                       \
+            else if (batch == 256) LAUNCH<16, 16, 256>(ARGS, n_tiles, s);                       \
+            else ok = false;                                                                    \
+        } else if (key == 32008) {                                                              \
+            if (batch == 64) LAUNCH<32, 8, 64>(ARGS, n_tiles, s);                               \
+            else if (batch == 128) LAUNCH<32, 8, 128>(ARGS, n_tiles, s);                        \
+            else if (batch == 256) LAUNCH<32, 8, 256>(ARGS, n_tiles, s);                        \
+            else ok = false;                                                                    \
+        } else {                                                                                \
+            ok = false;                                                                         \
+        }                                                                                       \
+        if (!ok) return hipErrorInvalidValue;                                                   \
+    } while (0)
+
+hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                            float *out_rgb, float *out_T, uint32_t *n_contrib,
+                            uint64_t *pair_counter, hipStream_t s) {
+    CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, n_contrib,
+               reinterpret_cast<unsigned long long *>(pair_counter)};
+    const int n_tiles = rp.tiles_x * rp.tiles_y;
+    FDGS_DISPATCH(launch_fwd, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+                                     const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                                     const float *T_final, const uint32_t *n_contrib,
+                                     const float *dL_drgb, float *g2d, int64_t /*n_proc_max*/,
+                                     hipStream_t s) {
+    BwdArgs a{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d};
+    const int n_tiles = rp.tiles_x * rp.tiles_y;
+    FDGS_DISPATCH(launch_bwd, a);
+    return hipGetLastError();
+}
+
+}  // namespace fdgs

@@ -1,0 +1,181 @@
+// Device-wide exclusive scans (reduce, scan of block sums, downsweep) and the
+// ballot-based compaction of active-set bits into ascending indices.
+#include <hip/hip_runtime.h>
+
+#include "dev_util.h"
+#include "fdgs_internal.h"
+
+namespace fdgs {
+namespace {
+
+constexpr int kNT = 256;         // threads per block
+constexpr int kItems = 8;        // items per thread
+constexpr int kChunk = kNT * kItems;
+constexpr int kTopNT = 1024;
+
+__device__ __forceinline__ int64_t count_of(const int64_t *n_dev, int64_t n_max) {
+    return n_dev ? min(*n_dev, n_max) : n_max;
+}
+
+// Loader for the scanned value of element j: flags (u8) or u32 counts,
+// optionally read through a gather index.
+struct LoadU8 {
+    const uint8_t *in;
+    __device__ __forceinline__ uint64_t operator()(int64_t j) const { return in[j]; }
+};
+struct LoadU32 {
+    const uint32_t *in;
+    const uint32_t *gather;
+    __device__ __forceinline__ uint64_t operator()(int64_t j) const {
+        return in[gather ? (int64_t)gather[j] : j];
+    }
+};
+
+template <typename Load>
+__global__ void __launch_bounds__(kNT) reduce_kernel(Load ld, const int64_t *n_dev, int64_t n_max,
+                                                     uint64_t *partial) {
+    __shared__ uint64_t tmp[kNT / 64 + 1];
+    const int64_t n = count_of(n_dev, n_max);
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        if (base + k < n) s += ld(base + k);
+    uint64_t total;
+    block_exclusive_sum<kNT>(s, tmp, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Exclusive scan of nb block sums by one block; writes the grand total.
+__global__ void __launch_bounds__(kTopNT) top_scan_kernel(uint64_t *partial, int64_t nb,
+                                                          int64_t *total) {
+    __shared__ uint64_t tmp[kTopNT / 64 + 1];
+    uint64_t carry = 0;
+    for (int64_t start = 0; start < nb; start += kTopNT) {
+        const int64_t j = start + threadIdx.x;
+        const uint64_t v = j < nb ? partial[j] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_sum<kTopNT>(v, tmp, &tot);
+        if (j < nb) partial[j] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = (int64_t)carry;
+}
+
+template <typename Load, typename Out>
+__global__ void __launch_bounds__(kNT) downsweep_kernel(Load ld, const int64_t *n_dev, int64_t n_max,
+                                                        const uint64_t *partial, Out *out) {
+    __shared__ uint64_t tmp[kNT / 64 + 1];
+    const int64_t n = count_of(n_dev, n_max);
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+    uint64_t v[kItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        v[k] = base + k < n ? ld(base + k) : 0;
+        s += v[k];
+    }
+    uint64_t total;
+    uint64_t run = block_exclusive_sum<kNT>(s, tmp, &total) + partial[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (base + k < n) out[base + k] = (Out)run;
+        run += v[k];
+    }
+}
+
+template <typename Load, typename Out>
+hipError_t scan_impl(Load ld, Out *out, const int64_t *n_dev, int64_t n_max, int64_t *total,
+                     void *scratch, hipStream_t s) {
+    const int64_t nb = (n_max + kChunk - 1) / kChunk;
+    uint64_t *partial = static_cast<uint64_t *>(scratch);
+    if (nb == 0) {
+        // still define the total
+        hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, (int64_t)0, total);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((reduce_kernel<Load>), dim3((unsigned)nb), dim3(kNT), 0, s, ld, n_dev, n_max, partial);
+    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total);
+    hipLaunchKernelGGL((downsweep_kernel<Load, Out>), dim3((unsigned)nb), dim3(kNT), 0, s, ld, n_dev,
+                       n_max, (const uint64_t *)partial, out);
+    return hipGetLastError();
+}
+
+// --- compaction of active-set bits -----------------------------------------
+// Each block covers kChunk Gaussians (kChunk/32 bit words).
+__global__ void __launch_bounds__(kNT) bits_count_kernel(const uint32_t *bits, int64_t nw,
+                                                         uint64_t *partial) {
+    __shared__ uint64_t tmp[kNT / 64 + 1];
+    constexpr int kWords = kChunk / 32;
+    const int64_t w0 = (int64_t)blockIdx.x * kWords;
+    uint64_t c = 0;
+    for (int k = threadIdx.x; k < kWords; k += kNT)
+        if (w0 + k < nw) c += __popc(bits[w0 + k]);
+    uint64_t total;
+    block_exclusive_sum<kNT>(c, tmp, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Thread t of round r handles Gaussian g = block_base + r*kNT + t.  A wave's
+// keep bits come from one ballot; a lane's rank is the popcount of the bits
+// below it (mbcnt); wave counts are combined through shared memory, so the
+// output stays in ascending order.
+__global__ void __launch_bounds__(kNT) bits_compact_kernel(const uint32_t *bits, int64_t n,
+                                                           const uint64_t *partial, uint32_t *idx) {
+    __shared__ uint64_t tmp[kNT / 64 + 1];
+    uint64_t run = partial[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t g = base + (int64_t)r * kNT + threadIdx.x;
+        const bool keep = g < n && ((bits[g >> 5] >> (g & 31)) & 1u);
+        const uint64_t ballot = __ballot(keep);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+        const uint64_t wcount = __popcll(ballot);
+        if (lane_id() == 0) tmp[wave_id()] = wcount;
+        __syncthreads();
+        uint64_t before = 0, round_total = 0;
+        for (int w = 0; w < kNT / 64; ++w) {
+            if (w < wave_id()) before += tmp[w];
+            round_total += tmp[w];
+        }
+        if (keep) idx[run + before + rank] = (uint32_t)g;
+        run += round_total;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t scan_scratch_bytes(int64_t n_max) {
+    return sizeof(uint64_t) * (size_t)((n_max + kChunk - 1) / kChunk + 1);
+}
+
+size_t compact_scratch_bytes(int64_t n) { return scan_scratch_bytes(n); }
+
+hipError_t scan_flags_u8(const uint8_t *in, uint32_t *out, const int64_t *n_dev, int64_t n_max,
+                         int64_t *total, void *scratch, hipStream_t s) {
+    return scan_impl(LoadU8{in}, out, n_dev, n_max, total, scratch, s);
+}
+
+hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t *out,
+                           const int64_t *n_dev, int64_t n_max, int64_t *total, void *scratch,
+                           hipStream_t s) {
+    return scan_impl(LoadU32{in, gather}, out, n_dev, n_max, total, scratch, s);
+}
+
+hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t *count,
+                        void *scratch, hipStream_t s) {
+    const int64_t nb = (n + kChunk - 1) / kChunk;
+    uint64_t *partial = static_cast<uint64_t *>(scratch);
+    const int64_t nw = (n + 31) / 32;
+    if (nb > 0)
+        hipLaunchKernelGGL(bits_count_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, nw, partial);
+    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, count);
+    if (nb > 0)
+        hipLaunchKernelGGL(bits_compact_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, n,
+                           (const uint64_t *)partial, idx);
+    return hipGetLastError();
+}
+
+}  // namespace fdgs

@@ -1,0 +1,313 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs with 8-bit
+// digits, plus the binning kernels around it: compaction of visible
+// Gaussians, exact float64 depth order, tile-key duplication and tile ranges.
+//
+// Depth order (Eq. 2 blends "sorted by depth"): the visible Gaussians are
+// sorted by the float32-rounded depth (4 digit passes over N_vis, stable, so
+// equal keys stay in processing order), and runs of equal float32 keys, which
+// are rare and short, are then re-ordered by the float64 depth and the
+// processing position.  Rounding is monotone, so the result is the order by
+// (float64 depth, position).
+//
+// Tile binning: instances are emitted in that depth order and then sorted
+// stably by tile id alone (ceil(tile_bits / 8) passes over the instances),
+// which yields each tile's list in depth order without sorting 64-bit
+// (tile, depth) keys over every instance.
+#include <hip/hip_runtime.h>
+
+#include "dev_util.h"
+#include "fdgs_internal.h"
+
+namespace fdgs {
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kRounds = 16;
+constexpr int kChunk = kNT * kRounds;   // keys per block
+constexpr int kRadix = 256;
+
+__device__ __forceinline__ int64_t count_of(const int64_t *n_dev, int64_t n_max) {
+    return n_dev ? min(*n_dev, n_max) : n_max;
+}
+
+// Per-block digit histogram, stored digit-major: hist[d * nb + b].
+__global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, const int64_t *n_dev,
+                                                      int64_t n_max, int shift, uint32_t mask,
+                                                      uint32_t *hist) {
+    __shared__ uint32_t h[kRadix];
+    const int64_t n = count_of(n_dev, n_max);
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t j = base + (int64_t)r * kNT + threadIdx.x;
+        if (j < n) atomicAdd(&h[(keys[j] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's per-block counts,
+// total into digit_total[d].
+__global__ void __launch_bounds__(1024) rowscan_kernel(uint32_t *hist, int64_t nb,
+                                                       uint32_t *digit_total) {
+    __shared__ uint32_t tmp[1024 / 64 + 1];
+    uint32_t *row = hist + (int64_t)blockIdx.x * nb;
+    uint32_t carry = 0;
+    for (int64_t start = 0; start < nb; start += 1024) {
+        const int64_t j = start + threadIdx.x;
+        const uint32_t v = j < nb ? row[j] : 0;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_sum<1024>(v, tmp, &tot);
+        if (j < nb) row[j] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+// Stable scatter.  Round r: thread t takes key base + r*kNT + t.  Lanes with
+// equal digits are found with one ballot per digit bit; a lane's rank is the
+// number of matching lanes below it; per-wave digit counts in shared memory
+// give the offsets of earlier waves; a running per-digit base carries across
+// rounds.  Thread t also owns digit t for the bookkeeping.
+__global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, const uint32_t *vals,
+                                                        uint32_t *keys_out, uint32_t *vals_out,
+                                                        const int64_t *n_dev, int64_t n_max,
+                                                        int shift, int bits, const uint32_t *hist,
+                                                        const uint32_t *digit_total) {
+    constexpr int NW = kNT / 64;
+    __shared__ uint32_t s_base[kRadix];      // next output slot of each digit for this block
+    __shared__ uint32_t s_cnt[NW][kRadix];   // per-wave digit counts -> offsets
+    __shared__ uint32_t s_tmp[kNT / 64 + 1];
+    const int64_t n = count_of(n_dev, n_max);
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const uint32_t mask = (1u << bits) - 1u;
+    const int dd = threadIdx.x;
+    {
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_sum<kNT>(digit_total[dd], s_tmp, &tot);
+        s_base[dd] = ex + hist[(int64_t)dd * gridDim.x + blockIdx.x];
+    }
+    const int lane = lane_id(), w = wave_id();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t rb = base + (int64_t)r * kNT;
+        if (rb >= n) break;                  // uniform across the block
+#pragma unroll
+        for (int k = 0; k < NW; ++k) s_cnt[k][dd] = 0;
+        __syncthreads();
+        const int64_t j = rb + threadIdx.x;
+        const bool valid = j < n;
+        uint32_t key = 0, val = 0, d = 0;
+        if (valid) {
+            key = keys[j];
+            val = vals[j];
+            d = (key >> shift) & mask;
+        }
+        uint64_t match = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            match &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = __popcll(match & lt_mask);
+        const uint32_t cnt = __popcll(match);
+        if (valid && rank == cnt - 1) s_cnt[w][d] = cnt;   // last lane of its group
+        __syncthreads();
+        uint32_t round_tot = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const uint32_t c = s_cnt[k][dd];
+            s_cnt[k][dd] = round_tot;
+            round_tot += c;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = s_base[d] + s_cnt[w][d] + rank;
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        s_base[dd] += round_tot;
+    }
+}
+
+// Visible Gaussians -> (float32 depth bits, position) at their compacted slot.
+__global__ void scatter_visible_kernel(const uint8_t *visible, const uint32_t *pos,
+                                       const uint64_t *depth_key, const int64_t *n_dev,
+                                       int64_t n_max, uint32_t *keys32, uint32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count_of(n_dev, n_max) || !visible[i]) return;
+    const double z = __longlong_as_double((long long)depth_key[i]);
+    keys32[pos[i]] = __float_as_uint((float)z);   // z > 0: bit order = value order
+    vals[pos[i]] = (uint32_t)i;
+}
+
+// Runs of equal float32 depth keys: insertion sort by (float64 depth, position).
+// Runs longer than kMaxTieRun (many Gaussians at one depth to float32
+// precision, which only constructed inputs produce) are left in processing
+// order and reported through *flag, bounding the work of one thread.
+constexpr int64_t kMaxTieRun = 4096;
+
+__global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t *depth_key,
+                                const int64_t *n_dev, int64_t n_max, int32_t *flag) {
+    const int64_t n = count_of(n_dev, n_max);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j + 1 >= n) return;
+    const uint32_t k = keys32[j];
+    if (keys32[j + 1] != k) return;
+    if (j > 0 && keys32[j - 1] == k) return;      // not the start of the run
+    int64_t e = j + 1;
+    while (e < n && e - j <= kMaxTieRun && keys32[e] == k) ++e;
+    if (e - j > kMaxTieRun) {
+        atomicOr(flag, 2);
+        return;
+    }
+    for (int64_t a = j + 1; a < e; ++a) {
+        const uint32_t v = vals[a];
+        const uint64_t dv = depth_key[v];
+        int64_t b = a - 1;
+        while (b >= j) {
+            const uint32_t u = vals[b];
+            const uint64_t du = depth_key[u];
+            if (du < dv || (du == dv && u < v)) break;
+            vals[b + 1] = u;
+            --b;
+        }
+        vals[b + 1] = v;
+    }
+}
+
+// One thread per visible Gaussian (in depth order) writes its tile keys.
+__global__ void duplicate_kernel(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
+                                 const int64_t *n_vis_dev, int64_t n_max, RenderParams rp,
+                                 uint32_t *tile_keys, uint32_t *ids, const int64_t *n_inst_dev,
+                                 int64_t capacity, int32_t *overflow) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count_of(n_vis_dev, n_max)) return;
+    if (j == 0 && *n_inst_dev > capacity) atomicOr(overflow, 1);
+    const uint32_t id = order[j];
+    const int4 r = reinterpret_cast<const int4 *>(rect)[id];
+    uint64_t off = offsets[j];
+    const int tx0 = r.x / rp.tile_w, tx1 = r.z / rp.tile_w;
+    const int ty0 = r.y / rp.tile_h, ty1 = r.w / rp.tile_h;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            if (off < (uint64_t)capacity) {
+                tile_keys[off] = (uint32_t)(ty * rp.tiles_x + tx);
+                ids[off] = id;
+            }
+            ++off;
+        }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) p[j] = v;
+}
+
+__global__ void ranges_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max,
+                              uint32_t *ranges) {
+    const int64_t n = count_of(n_dev, n_max);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t t = keys[j];
+    if (j == 0 || keys[j - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)j;
+    if (j == n - 1 || keys[j + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(j + 1);
+}
+
+__global__ void accumulate_counts_kernel(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
+                                         int64_t capacity, unsigned long long *acc) {
+    if (threadIdx.x != 0) return;
+    const int64_t p = n_proc_dev ? min(*n_proc_dev, n_proc) : n_proc;
+    atomicAdd(acc + 0, (unsigned long long)p);
+    atomicAdd(acc + 1, (unsigned long long)counts[0]);
+    atomicAdd(acc + 2, (unsigned long long)min(counts[1], capacity));
+}
+
+inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+}  // namespace
+
+size_t sort_scratch_bytes(int64_t n_max) {
+    const int64_t nb = (n_max + kChunk - 1) / kChunk;
+    return sizeof(uint32_t) * (size_t)(kRadix * (nb > 0 ? nb : 1) + kRadix);
+}
+
+hipError_t radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                          const int64_t *n_dev, int64_t n_max, int begin_bit, int end_bit,
+                          void *scratch, int *result_in_alt, hipStream_t s) {
+    *result_in_alt = 0;
+    const int64_t nb = (n_max + kChunk - 1) / kChunk;
+    if (nb == 0 || end_bit <= begin_bit) return hipSuccess;
+    uint32_t *hist = static_cast<uint32_t *>(scratch);
+    uint32_t *digit_total = hist + (size_t)kRadix * nb;
+    uint32_t *src_k = keys, *src_v = vals, *dst_k = keys_alt, *dst_v = vals_alt;
+    int alt = 0;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        const int bits = min(8, end_bit - shift);
+        const uint32_t mask = (1u << bits) - 1u;
+        hipLaunchKernelGGL(upsweep_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, src_k, n_dev, n_max,
+                           shift, mask, hist);
+        hipLaunchKernelGGL(rowscan_kernel, dim3(kRadix), dim3(1024), 0, s, hist, nb, digit_total);
+        hipLaunchKernelGGL(downsweep_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, src_k, src_v,
+                           dst_k, dst_v, n_dev, n_max, shift, bits, (const uint32_t *)hist,
+                           (const uint32_t *)digit_total);
+        uint32_t *tk = src_k, *tv = src_v;
+        src_k = dst_k; src_v = dst_v; dst_k = tk; dst_v = tv;
+        alt ^= 1;
+    }
+    *result_in_alt = alt;
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_visible(const uint8_t *visible, const uint32_t *pos,
+                                  const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
+                                  uint32_t *keys32, uint32_t *vals, hipStream_t s) {
+    if (n_max == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_visible_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, visible,
+                       pos, depth_key, n_dev, n_max, keys32, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_t *depth_key,
+                                 const int64_t *n_vis_dev, int64_t n_max, int32_t *flag, hipStream_t s) {
+    if (n_max == 0) return hipSuccess;
+    hipLaunchKernelGGL(fix_ties_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, keys32, vals,
+                       depth_key, n_vis_dev, n_max, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
+                            const int64_t *n_vis_dev, int64_t n_max, const RenderParams &rp,
+                            uint32_t *tile_keys, uint32_t *ids, const int64_t *n_inst_dev,
+                            int64_t capacity, int32_t *overflow, hipStream_t s) {
+    if (n_max == 0) return hipSuccess;
+    hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, order, offsets,
+                       rect, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
+                                    int64_t capacity, uint64_t *acc, hipStream_t s) {
+    hipLaunchKernelGGL(accumulate_counts_kernel, dim3(1), dim3(64), 0, s, n_proc_dev, n_proc, counts, capacity,
+                       reinterpret_cast<unsigned long long *>(acc));
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
+                              int32_t n_tiles, uint32_t *ranges, hipStream_t s) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(2 * (int64_t)n_tiles, 256)), dim3(256), 0, s,
+                       ranges, 2 * (int64_t)n_tiles, 0u);
+    if (n_max > 0)
+        hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, tile_keys,
+                           n_inst_dev, n_max, ranges);
+    return hipGetLastError();
+}
+
+}  // namespace fdgs

@@ -1,0 +1,246 @@
+"""Torch-facing wrapper of libfdgs: device tensors in, device tensors out.
+
+PyTorch only provides device memory and the stream; every computation runs
+in the library's HIP kernels.  See include/fdgs.h for the semantics of each
+call.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_HIP = None
+
+
+def _hip():
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _HIP.hipMemcpy.restype = ctypes.c_int
+    return _HIP
+
+
+def _copy_device(dst: torch.Tensor, src_ptr: int, nbytes: int) -> None:
+    if nbytes == 0:
+        return
+    rc = _hip().hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), ctypes.c_size_t(nbytes), 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class GaussianModel:
+    """4D Gaussians as float32 structure-of-arrays device tensors."""
+
+    FIELDS = ("mean", "log_scale", "q_left", "q_right", "opacity_logit", "sh")
+
+    def __init__(self, mean, log_scale, q_left, q_right, opacity_logit, sh, sh_degree: int = 3):
+        self.mean, self.log_scale = mean, log_scale
+        self.q_left, self.q_right = q_left, q_right
+        self.opacity_logit, self.sh = opacity_logit, sh
+        self.sh_degree = int(sh_degree)
+        n = mean.shape[1]
+        shapes = {"mean": (4, n), "log_scale": (4, n), "q_left": (4, n), "q_right": (4, n),
+                  "opacity_logit": (n,), "sh": (16, 3, n)}
+        for k, shp in shapes.items():
+            t = getattr(self, k)
+            if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{k}: need a contiguous float32 device tensor of shape {shp}")
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[1])
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda"):
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        return cls(t(scene.mean), t(scene.log_scale), t(scene.q_left), t(scene.q_right),
+                   t(scene.opacity_logit), t(scene.sh), scene.sh_degree)
+
+    def struct(self) -> _lib.Model:
+        m = _lib.Model()
+        for k in self.FIELDS:
+            setattr(m, k, getattr(self, k).data_ptr())
+        m.n = self.n
+        m.sh_degree = self.sh_degree
+        return m
+
+    def tensors(self):
+        return [getattr(self, k) for k in self.FIELDS]
+
+
+class State:
+    """Handle of a forward pass kept for the adjoint or for inspection."""
+
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p, shape):
+        self.ctx, self.handle, self.shape = ctx, handle, shape
+
+    def release(self):
+        if self.handle is not None and self.handle.value:
+            self.ctx.release(self)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        self.handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.fdgs_create(ctypes.byref(self.handle), device))
+
+    def close(self):
+        if self.handle.value:
+            torch.cuda.synchronize(self.device)
+            _lib.check(self.lib.fdgs_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # (1) ------------------------------------------------------------------
+    def slice_4d(self, model: GaussianModel, t: float, idx: Optional[torch.Tensor] = None):
+        m = model.n if idx is None else int(idx.numel())
+        dev = self.device
+        mean3 = torch.empty((3, m), dtype=torch.float32, device=dev)
+        cov3 = torch.empty((6, m), dtype=torch.float32, device=dev)
+        p = torch.empty((m,), dtype=torch.float32, device=dev)
+        ms = model.struct()
+        _lib.check(self.lib.fdgs_slice_4d(self.handle, ctypes.byref(ms), float(t), _ptr(idx), m,
+                                          _ptr(mean3), _ptr(cov3), _ptr(p), _stream(dev)))
+        return mean3, cov3, p
+
+    # (2) ------------------------------------------------------------------
+    def build_active_mask(self, model: GaussianModel, frame_times, key_lo: float, key_hi: float,
+                          mode: int = _lib.MASK_TEMPORAL, views=(), alpha_min: float = 0.0,
+                          dilation: float = -1.0):
+        n = model.n
+        dev = self.device
+        bits = torch.empty(((n + 31) // 32,), dtype=torch.int32, device=dev)
+        idx = torch.empty((max(n, 1),), dtype=torch.int32, device=dev)
+        count = torch.zeros((1,), dtype=torch.int64, device=dev)
+        ft = np.ascontiguousarray(np.asarray(frame_times, dtype=np.float64))
+        cams = (_lib.Camera * max(len(views), 1))(*[_lib.camera_struct(v) for v in views])
+        spec = _lib.MaskSpec()
+        spec.frame_times = ft.ctypes.data
+        spec.n_frames = ft.size
+        spec.views = ctypes.cast(cams, ctypes.c_void_p)
+        spec.n_views = len(views)
+        spec.key_lo, spec.key_hi = float(key_lo), float(key_hi)
+        spec.mode = int(mode)
+        spec.alpha_min = float(alpha_min)
+        spec.dilation = float(dilation)
+        ms = model.struct()
+        _lib.check(self.lib.fdgs_build_active_mask(self.handle, ctypes.byref(ms), ctypes.byref(spec),
+                                                   _ptr(bits), _ptr(idx), _ptr(count), _stream(dev)))
+        return bits, idx, count
+
+    # (3) ------------------------------------------------------------------
+    def render(self, model: GaussianModel, cam, t: float, cfg: Optional[_lib.RenderCfg] = None,
+               idx: Optional[torch.Tensor] = None, n_idx: Optional[torch.Tensor] = None,
+               want_T: bool = False, keep_state=False, out_rgb: Optional[torch.Tensor] = None):
+        """keep_state: False, True (new state) or an existing State to reuse."""
+        cfg = cfg if cfg is not None else _lib.default_cfg()
+        cs = _lib.camera_struct(cam)
+        dev = self.device
+        H, W = cs.height, cs.width
+        rgb = out_rgb if out_rgb is not None else torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        T = torch.empty((H, W), dtype=torch.float32, device=dev) if want_T else None
+        ms = model.struct()
+        st_ptr = None
+        handle = None
+        if keep_state is not False and keep_state is not None:
+            handle = keep_state.handle if isinstance(keep_state, State) else ctypes.c_void_p()
+            st_ptr = ctypes.byref(handle)
+        _lib.check(self.lib.fdgs_render_forward(self.handle, ctypes.byref(ms), _ptr(idx), _ptr(n_idx),
+                                                ctypes.byref(cs), float(t), ctypes.byref(cfg), _ptr(rgb),
+                                                _ptr(T), st_ptr, _stream(dev)))
+        state = None
+        if handle is not None:
+            state = keep_state if isinstance(keep_state, State) else State(self, handle, (H, W))
+        return rgb, T, state
+
+    # (4) ------------------------------------------------------------------
+    def backward(self, state: State, dL_drgb: torch.Tensor, model: GaussianModel, grads=None):
+        if grads is None:
+            grads = {k: torch.zeros_like(getattr(model, k)) for k in GaussianModel.FIELDS}
+        g = _lib.Grads()
+        for k in GaussianModel.FIELDS:
+            setattr(g, k, grads[k].data_ptr())
+        dL = dL_drgb.contiguous()
+        _lib.check(self.lib.fdgs_render_backward(self.handle, state.handle, _ptr(dL), ctypes.byref(g),
+                                                 _stream(self.device)))
+        return grads
+
+    def release(self, state: State):
+        _lib.check(self.lib.fdgs_state_release(self.handle, state.handle))
+        state.handle = ctypes.c_void_p()
+
+    def binning(self, state: State) -> dict:
+        b = _lib.Binning()
+        _lib.check(self.lib.fdgs_state_binning(self.handle, state.handle, ctypes.byref(b), _stream(self.device)))
+        dev = self.device
+        out = {
+            "sorted_ids": torch.empty((b.n_inst,), dtype=torch.int32, device=dev),
+            "tile_ranges": torch.empty((b.n_tiles, 2), dtype=torch.int32, device=dev),
+            "rects": torch.empty((b.n_proc, 4), dtype=torch.int32, device=dev),
+            "depth": torch.empty((b.n_proc,), dtype=torch.float64, device=dev),
+            "visible": torch.empty((b.n_proc,), dtype=torch.uint8, device=dev),
+        }
+        _copy_device(out["sorted_ids"], b.sorted_ids, 4 * b.n_inst)
+        _copy_device(out["tile_ranges"], b.tile_ranges, 8 * b.n_tiles)
+        _copy_device(out["rects"], b.rects, 16 * b.n_proc)
+        _copy_device(out["depth"], b.depth, 8 * b.n_proc)
+        _copy_device(out["visible"], b.visible, b.n_proc)
+        out.update(n_inst=b.n_inst, n_vis=b.n_vis, n_proc=b.n_proc, n_tiles=b.n_tiles,
+                   tiles_x=b.tiles_x, tiles_y=b.tiles_y)
+        return out
+
+    def check_overflow(self):
+        _lib.check(self.lib.fdgs_check_overflow(self.handle, _stream(self.device)))
+
+    def profile(self, enable: bool):
+        _lib.check(self.lib.fdgs_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        p = _lib.Profile()
+        _lib.check(self.lib.fdgs_profile_read(self.handle, ctypes.byref(p), 1 if reset else 0))
+        return {"ms": {name: p.ms[k] for k, name in enumerate(_lib.STAGES)},
+                "calls": {name: p.calls[k] for k, name in enumerate(_lib.STAGES)},
+                "processed": p.processed, "visible": p.visible, "instances": p.instances, "pairs": p.pairs}
+
+
+class Render4DGS(torch.autograd.Function):
+    """rgb = Render4DGS.apply(context, cam, t, cfg, idx, n_idx, mean, log_scale, q_left, q_right,
+    opacity_logit, sh).  The backward runs the library's adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, context: Context, cam, t, cfg, idx, n_idx, mean, log_scale, q_left, q_right,
+                opacity_logit, sh):
+        model = GaussianModel(mean.detach(), log_scale.detach(), q_left.detach(), q_right.detach(),
+                              opacity_logit.detach(), sh.detach())
+        rgb, _, state = context.render(model, cam, t, cfg, idx=idx, n_idx=n_idx, keep_state=True)
+        ctx.context, ctx.state, ctx.model = context, state, model
+        return rgb
+
+    @staticmethod
+    def backward(ctx, dL_drgb):
+        grads = ctx.context.backward(ctx.state, dL_drgb, ctx.model)
+        ctx.context.release(ctx.state)
+        g = [grads[k] for k in GaussianModel.FIELDS]
+        return (None, None, None, None, None, None, *g)

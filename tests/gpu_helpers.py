@@ -1,0 +1,55 @@
+"""Shared helpers for the GPU parity tests (inputs and tolerances only)."""
+import numpy as np
+import pytest
+
+from oracle import composite as oc
+
+F32 = lambda x: float(np.float32(x))
+
+# Image tolerance: max |GPU - FP64 oracle| per channel, over pixels the oracle
+# does not flag as sitting within 1e-5 (alpha) / 1e-4 (transmittance) of a
+# threshold decision.
+IMG_TOL = 1e-4
+# A flagged pixel can differ by at most one near-threshold contribution.
+FLAG_TOL = 2e-2
+MAX_FLAGGED_FRAC = 5e-4
+
+
+def oracle_settings(cfg=None, **kw) -> oc.Settings:
+    """Oracle settings with the float32 values the library receives."""
+    base = dict(alpha_min=F32(1 / 255), alpha_max=F32(0.99), t_min=F32(1e-4), dilation=F32(0.3),
+                bg=(0.0, 0.0, 0.0), temporal_cull=True, tile_w=16, tile_h=16)
+    if cfg is not None:
+        base.update(alpha_min=float(cfg.alpha_min), alpha_max=float(cfg.alpha_max), t_min=float(cfg.t_min),
+                    dilation=float(cfg.dilation), bg=tuple(float(cfg.bg[i]) for i in range(3)),
+                    temporal_cull=bool(cfg.temporal_cull), tile_w=cfg.tile_w, tile_h=cfg.tile_h)
+    base.update(kw)
+    return oc.Settings(**base)
+
+
+def compare_image(gpu_rgb, ref, *, tol=IMG_TOL, pixels=None):
+    """gpu_rgb (3, H, W) numpy; ref an oracle Image (full or sampled)."""
+    if pixels is None:
+        g = gpu_rgb.reshape(3, -1)
+        r = ref.rgb.reshape(3, -1)
+        f = ref.flags.reshape(-1)
+    else:
+        px, py = pixels
+        g = gpu_rgb[:, py, px]
+        r = ref.rgb
+        f = ref.flags
+    err = np.abs(g - r).max(axis=0)
+    clean = f == 0
+    n_flag = int((~clean).sum())
+    worst = float(err[clean].max()) if clean.any() else 0.0
+    worst_flag = float(err[~clean].max()) if n_flag else 0.0
+    assert worst <= tol, f"max |err| {worst:.3e} over unflagged pixels"
+    assert n_flag <= max(2, MAX_FLAGGED_FRAC * f.size), f"{n_flag} flagged pixels"
+    assert worst_flag <= FLAG_TOL, f"flagged pixel error {worst_flag:.3e}"
+    return worst, n_flag
+
+
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")

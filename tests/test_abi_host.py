@@ -1,0 +1,65 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, and rejects invalid arguments before any
+HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2503_16422_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "fdgs.h")).read()
+    return sorted(set(re.findall(r"FDGS_API[^;(]*?\b(fdgs_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libfdgs.so is not built")
+    return _lib.load()
+
+
+def test_exports_match_header(lib):
+    syms = header_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(_lib.EXPORTS) == syms
+
+
+def test_version_and_defaults(lib):
+    assert b"gfx950" in lib.fdgs_version()
+    cfg = _lib.default_cfg()
+    assert (cfg.tile_w, cfg.tile_h, cfg.batch) == (16, 16, 128)
+    assert abs(cfg.alpha_min - 1 / 255) < 1e-8 and cfg.temporal_cull == 1
+
+
+def test_null_context_rejected_without_gpu(lib):
+    m = _lib.Model()
+    st = lib.fdgs_slice_4d(None, ctypes.byref(m), 0.5, None, 0, None, None, None, None)
+    assert st == _lib.FDGS_ERR_INVALID_ARG
+    assert b"ctx" in lib.fdgs_last_error()
+    cam = _lib.Camera()
+    cfg = _lib.default_cfg()
+    st = lib.fdgs_render_forward(None, ctypes.byref(m), None, None, ctypes.byref(cam), 0.5,
+                                 ctypes.byref(cfg), None, None, None, None)
+    assert st == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_render_backward(None, None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_build_active_mask(None, None, None, None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_state_release(None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_check_overflow(None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_create(None, 0) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_destroy(None) == _lib.FDGS_OK
+
+
+def test_struct_layouts_match_header():
+    # sizes follow the C layout rules for the declared members
+    assert ctypes.sizeof(_lib.Model) == 6 * 8 + 8 + 8
+    assert ctypes.sizeof(_lib.Camera) == 9 * 8 + 3 * 8 + 5 * 8 + 2 * 4
+    assert ctypes.sizeof(_lib.RenderCfg) == 3 * 4 + 3 * 4 + 4 * 4 + 4 + 4 + 8
+    assert ctypes.sizeof(_lib.Grads) == 6 * 8

@@ -1,0 +1,286 @@
+"""GPU parity of the forward path against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import binning as obin
+from oracle import composite as oc
+from oracle import mask as omask
+from oracle import slicing as osl
+from paper_2503_16422_amd import _lib, inputs
+from tests.gpu_helpers import compare_image, oracle_settings
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2503_16422_amd.render import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(scene):
+    from paper_2503_16422_amd.render import GaussianModel
+    return GaussianModel.from_scene(scene, "cuda:0")
+
+
+# a1/a2 ------------------------------------------------------------------------
+@pytest.mark.parametrize("use_idx", [False, True])
+def test_slice_4d_matches_eq1(ctx, use_idx):
+    sc = inputs.tiny_scene(10_000, seed=0)
+    model = to_dev(sc)
+    idx = None
+    sel = np.arange(sc.n)
+    if use_idx:
+        sel = np.sort(np.random.default_rng(1).choice(sc.n, 3001, replace=False))
+        idx = torch.from_numpy(sel.astype(np.int32)).cuda()
+    mean3, cov3, p = ctx.slice_4d(model, 0.5, idx)
+    torch.cuda.synchronize()
+    M, LS, QL, QR = (osl.rows(a)[sel] for a in (sc.mean, sc.log_scale, sc.q_left, sc.q_right))
+    m_ref, c_ref, p_ref = osl.slice_at(M, LS, QL, QR, 0.5)
+    g_m = mean3.cpu().numpy().T
+    g_c = cov3.cpu().numpy().T
+    g_p = p.cpu().numpy()
+    assert np.abs(g_m - m_ref).max() <= 1e-6 * (1 + np.abs(m_ref).max())
+    iu = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    c_ref6 = np.stack([c_ref[:, i, j] for i, j in iu], 1)
+    scale = np.abs(c_ref6).max(axis=1, keepdims=True)
+    assert (np.abs(g_c - c_ref6) <= 1e-6 * scale + 1e-30).all()
+    assert np.abs(g_p - p_ref).max() <= 1e-7
+
+
+# a6 image parity ------------------------------------------------------------------
+def test_tiny_render_matches_oracle(ctx):
+    sc = inputs.tiny_scene(10_000, seed=0)
+    cam = inputs.look_at_camera(0.0, 3.0, 256, 256)
+    model = to_dev(sc)
+    rgb, T, _ = ctx.render(model, cam, 0.5, want_T=True)
+    torch.cuda.synchronize()
+    st = oracle_settings()
+    ref = oc.render(sc.arrays(), cam, 0.5, st, mode="rect")
+    worst, nflag = compare_image(rgb.cpu().numpy(), ref)
+    assert np.abs(T.cpu().numpy() - ref.T)[ref.flags == 0].max() <= 1e-4
+    print(f"tiny render: max err {worst:.2e}, flagged {nflag}")
+
+
+@pytest.mark.parametrize("W,H,bg", [(37, 29, (0.0, 0.0, 0.0)), (100, 61, (0.2, 0.5, 1.0)), (1, 1, (0.3, 0.3, 0.3))])
+def test_ragged_images_and_background(ctx, W, H, bg):
+    sc = inputs.tiny_scene(3000, seed=4)
+    sc.log_scale[:3] += 1.0
+    cam = inputs.look_at_camera(10.0, 3.0, W, H)
+    model = to_dev(sc)
+    cfg = _lib.default_cfg(bg=bg)
+    rgb, _, _ = ctx.render(model, cam, 0.4, cfg)
+    torch.cuda.synchronize()
+    ref = oc.render(sc.arrays(), cam, 0.4, oracle_settings(cfg), mode="brute")
+    compare_image(rgb.cpu().numpy(), ref)
+
+
+def test_empty_and_invisible_scenes(ctx):
+    cam = inputs.look_at_camera(0.0, 3.0, 48, 40)
+    cfg = _lib.default_cfg(bg=(0.25, 0.5, 0.75))
+    bg = torch.tensor([0.25, 0.5, 0.75], device="cuda")[:, None, None].expand(3, 40, 48)
+    rgb, T, _ = ctx.render(_empty_model(), cam, 0.5, cfg, want_T=True)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, bg) and torch.all(T == 1)
+    # every Gaussian behind the camera
+    sc = inputs.tiny_scene(500, seed=1)
+    rgb, _, st = ctx.render(to_dev(sc), _looking_away(48, 40), 0.5, cfg, keep_state=True)
+    b = ctx.binning(st)
+    assert b["n_inst"] == 0 and b["n_vis"] == 0
+    assert torch.equal(rgb, bg)
+    ctx.release(st)
+
+
+def _looking_away(W, H):
+    c = inputs.look_at_camera(180.0, 3.0, W, H)      # at (0, 0, -3) facing the origin
+    c.R = np.stack([-c.R[0], c.R[1], -c.R[2]])       # turn around, keep a right-handed frame
+    c.tvec = -c.R @ np.array([0.0, 0.0, -3.0])
+    return c
+
+
+def _empty_model():
+    from paper_2503_16422_amd.render import GaussianModel
+    z = lambda *s: torch.zeros(s, dtype=torch.float32, device="cuda")
+    return GaussianModel(z(4, 0), z(4, 0), z(4, 0), z(4, 0), z(0), z(16, 3, 0))
+
+
+def test_degenerate_gaussians_are_culled(ctx):
+    sc = inputs.tiny_scene(400, seed=2)
+    sc.log_scale[:3] += 1.0
+    sc.q_left[:, 3] = 0.0          # zero quaternion
+    sc.mean[0, 5] = np.nan
+    sc.log_scale[1, 7] = np.inf
+    sc.opacity_logit[9] = -np.inf
+    cam = inputs.look_at_camera(0.0, 3.0, 64, 64)
+    rgb, _, _ = ctx.render(to_dev(sc), cam, 0.5)
+    torch.cuda.synchronize()
+    assert torch.isfinite(rgb).all()
+    keep = np.setdiff1d(np.arange(sc.n), [3, 5, 7, 9])
+    ref = oc.render(sc.subset(keep).arrays(), cam, 0.5, oracle_settings(), mode="brute")
+    compare_image(rgb.cpu().numpy(), ref)
+
+
+# a4/a5 binning -------------------------------------------------------------------
+@pytest.mark.parametrize("cull", [1, 0])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_binning_bit_exact(ctx, cull, tile):
+    sc = inputs.tiny_scene(10_000, seed=0)
+    cam = inputs.look_at_camera(0.0, 3.0, 256, 256)
+    cfg = _lib.default_cfg(temporal_cull=cull, tile_w=tile[0], tile_h=tile[1])
+    rgb, _, st = ctx.render(to_dev(sc), cam, 0.5, cfg, keep_state=True)
+    b = ctx.binning(st)
+    torch.cuda.synchronize()
+    ost = oracle_settings(cfg)
+    pre = oc.prepare(sc.arrays(), cam, 0.5, ost)
+    vis = b["visible"].cpu().numpy().astype(bool)
+    assert np.array_equal(vis, pre.visible)
+    rects = b["rects"].cpu().numpy()
+    assert np.array_equal(rects[vis], pre.rect[vis])
+    ids, tiles, ranges = obin.bin_gaussians(pre.rect, pre.depth, pre.visible, 256, 256, *tile)
+    assert b["n_inst"] == ids.size
+    assert np.array_equal(b["sorted_ids"].cpu().numpy().astype(np.uint32), ids)
+    assert_same_ranges(b["tile_ranges"].cpu().numpy().astype(np.uint32), ranges)
+    # and the same integer work from the library's own exported rects / depths
+    ids2, _, ranges2 = obin.bin_gaussians(rects, b["depth"].cpu().numpy(), vis, 256, 256, *tile)
+    assert np.array_equal(ids2, ids) and np.array_equal(ranges2, ranges)
+    ctx.release(st)
+
+
+def test_depth_ties_ordered_by_position(ctx):
+    # several Gaussians share an exact depth (same mean); order must follow index
+    sc = inputs.tiny_scene(300, seed=3)
+    sc.log_scale[:3] += 1.2
+    sc.mean[:, 100:140] = sc.mean[:, 100:101]
+    sc.log_scale[:, 100:140] = sc.log_scale[:, 100:101]
+    sc.q_left[:, 100:140] = sc.q_left[:, 100:101]
+    sc.q_right[:, 100:140] = sc.q_right[:, 100:101]
+    cam = inputs.look_at_camera(0.0, 3.0, 64, 64)
+    rgb, _, st = ctx.render(to_dev(sc), cam, float(sc.mean[3, 100]), keep_state=True)
+    b = ctx.binning(st)
+    torch.cuda.synchronize()
+    pre = oc.prepare(sc.arrays(), cam, float(sc.mean[3, 100]), oracle_settings())
+    ids, _, ranges = obin.bin_gaussians(pre.rect, pre.depth, pre.visible, 64, 64, 16, 16)
+    assert np.array_equal(b["sorted_ids"].cpu().numpy().astype(np.uint32), ids)
+    assert_same_ranges(b["tile_ranges"].cpu().numpy().astype(np.uint32), ranges)
+    ref = oc.composite(pre, cam, oracle_settings(), mode="brute")
+    compare_image(rgb.cpu().numpy(), ref)
+    ctx.release(st)
+
+
+def assert_same_ranges(got, ref):
+    """Non-empty tiles must match exactly; an empty tile may be any [s, s)."""
+    nonempty = ref[:, 1] > ref[:, 0]
+    bad = np.flatnonzero(nonempty & np.any(got != ref, axis=1))
+    assert bad.size == 0, f"{bad.size} tiles differ, first {bad[:5]}"
+    assert np.all(got[~nonempty, 0] == got[~nonempty, 1]), "an empty tile has a non-empty range"
+
+
+# invariances -------------------------------------------------------------------------
+def test_tile_and_batch_configs_give_identical_images(ctx):
+    sc = inputs.tiny_scene(10_000, seed=0)
+    cam = inputs.look_at_camera(0.0, 3.0, 200, 150)
+    model = to_dev(sc)
+    base = None
+    for tile in ((16, 16), (8, 8), (32, 8)):
+        for batch in (64, 128, 256):
+            for cull in (1, 0):
+                cfg = _lib.default_cfg(tile_w=tile[0], tile_h=tile[1], batch=batch, temporal_cull=cull)
+                rgb, _, _ = ctx.render(model, cam, 0.5, cfg)
+                if base is None:
+                    base = rgb.clone()
+                else:
+                    assert torch.equal(rgb, base), (tile, batch, cull)
+
+
+def test_forward_is_deterministic(ctx):
+    sc = inputs.long_scene(20_000, seed=1)
+    cam = inputs.arc_cameras(20, 4.0, 320, 240)[7]
+    model = to_dev(sc)
+    a, _, sa = ctx.render(model, cam, 0.3, keep_state=True)
+    ba = ctx.binning(sa)
+    b, _, sb = ctx.render(model, cam, 0.3, keep_state=True)
+    bb = ctx.binning(sb)
+    assert torch.equal(a, b)
+    assert torch.equal(ba["sorted_ids"], bb["sorted_ids"]) and torch.equal(ba["tile_ranges"], bb["tile_ranges"])
+    ctx.release(sa)
+    ctx.release(sb)
+
+
+def test_fixed_capacity_and_overflow(ctx):
+    sc = inputs.tiny_scene(10_000, seed=0)
+    cam = inputs.look_at_camera(0.0, 3.0, 256, 256)
+    model = to_dev(sc)
+    ref, _, st = ctx.render(model, cam, 0.5, keep_state=True)
+    m = ctx.binning(st)["n_inst"]
+    ctx.release(st)
+    ctx.check_overflow()
+    big, _, _ = ctx.render(model, cam, 0.5, _lib.default_cfg(instance_capacity=m + 1000))
+    ctx.check_overflow()
+    assert torch.equal(big, ref)
+    ctx.render(model, cam, 0.5, _lib.default_cfg(instance_capacity=max(1, m // 2)))
+    with pytest.raises(_lib.FdgsError) as e:
+        ctx.check_overflow()
+    assert e.value.code == _lib.FDGS_ERR_CAPACITY
+    ctx.check_overflow()   # flag cleared
+
+
+# a1 masks ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1])
+def test_active_mask_bit_exact(ctx, mode):
+    sc = inputs.long_scene(30_000, seed=2)
+    views = inputs.arc_cameras(5, 4.0, 338, 254)
+    frames = inputs.frame_times(300)[110:121]
+    bits, idx, count = ctx.build_active_mask(to_dev(sc), frames, frames[0], frames[-1], mode, views)
+    torch.cuda.synchronize()
+    keep, rbits, ridx = omask.active_mask(sc.arrays(), frames, frames[0], frames[-1], mode, views,
+                                          dilation=float(np.float32(0.3)), alpha_min=float(np.float32(1 / 255)))
+    n = int(count.item())
+    assert n == ridx.size
+    assert np.array_equal(bits.cpu().numpy().view(np.uint32), rbits)
+    assert np.array_equal(idx[:n].cpu().numpy().view(np.uint32), ridx)
+
+
+def test_temporal_mask_render_identical_to_dense(ctx):
+    sc = inputs.long_scene(40_000, seed=5)
+    cam = inputs.arc_cameras(20, 4.0, 338, 254)[3]
+    model = to_dev(sc)
+    frames = inputs.frame_times(300)[60:71]
+    bits, idx, count = ctx.build_active_mask(model, frames, frames[0], frames[-1], 0)
+    assert 0 < int(count.item()) < sc.n
+    for f in (0, 4, 10):
+        t = float(frames[f])
+        dense, _, _ = ctx.render(model, cam, t)
+        masked, _, _ = ctx.render(model, cam, t, idx=idx, n_idx=count)
+        assert torch.equal(dense, masked)
+
+
+# full-size sampled parity -------------------------------------------------------------
+def test_full_resolution_masked_frame_sampled(ctx):
+    sc = inputs.long_scene(200_000, seed=0)
+    cams = inputs.arc_cameras(20, 4.0, 1352, 1014)
+    model = to_dev(sc)
+    frames = inputs.frame_times(300)
+    keys, windows, fw = inputs.keyframe_windows(300, 10)
+    f = 137
+    lo, hi = windows[fw[f]]
+    win = frames[lo:hi + 1]
+    bits, idx, count = ctx.build_active_mask(model, win, frames[lo], frames[hi], 1, cams)
+    cam = cams[11]
+    rgb, _, _ = ctx.render(model, cam, float(frames[f]), idx=idx, n_idx=count)
+    torch.cuda.synchronize()
+    n = int(count.item())
+    sel = idx[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    rng = np.random.default_rng(7)
+    px = rng.integers(0, 1352, 4096)
+    py = rng.integers(0, 1014, 4096)
+    # plus two whole 16x16 tiles, one of them at the ragged bottom edge
+    ty, tx = np.meshgrid(np.arange(16), np.arange(16), indexing="ij")
+    px = np.concatenate([px, 16 * 40 + tx.ravel(), 16 * 84 + tx.ravel() % 8])
+    py = np.concatenate([py, 16 * 30 + ty.ravel(), 16 * 63 + ty.ravel() % 6])
+    st = oracle_settings()
+    ref = oc.render(sc.arrays(), cam, float(frames[f]), st, idx=sel, mode="rect", pixels=(px, py))
+    worst, nflag = compare_image(rgb.cpu().numpy(), ref, pixels=(px, py))
+    print(f"1352x1014 masked frame: {n}/{sc.n} kept, max err {worst:.2e}, flagged {nflag}")
