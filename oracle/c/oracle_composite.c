@@ -19,7 +19,8 @@
  *
  * Flags (per pixel, OR-ed): 1 an alpha within rel_alpha of alpha_min,
  * 2 a transmittance test within rel_t of t_min, 4 two consecutive
- * contributors whose depths differ by at most rel_depth * depth.
+ * contributors whose depths differ, but by at most rel_depth * depth (exactly
+ * equal depths are ordered by index, which is not ambiguous).
  */
 #include <math.h>
 #include <stdint.h>
@@ -57,7 +58,10 @@ static void shade_pixel(const oracle_scene *s, const int64_t *list, int64_t nlis
         const double test = T * (1.0 - alpha);
         if (fabs(test - s->t_min) <= s->rel_t * s->t_min) flag |= 2;
         if (test < s->t_min) break;
-        if (s->depth[i] - prev_depth <= s->rel_depth * fabs(s->depth[i])) flag |= 4;
+        {   /* equal depths are ordered by index on both sides; only near-equal ones are ambiguous */
+            const double gap = s->depth[i] - prev_depth;
+            if (gap > 0.0 && gap <= s->rel_depth * fabs(s->depth[i])) flag |= 4;
+        }
         prev_depth = s->depth[i];
         const double w = alpha * T;
         C0 += s->rgb[3 * i + 0] * w;

@@ -10,8 +10,8 @@
 // exponential and a dozen FMAs, not a contraction.
 //
 // Precision: the centre is stored as a float pair (hi + lo) and re-centred on
-// the tile while staging, so the per-pair offset dx = px + 0.5 - u is exact to
-// ~1e-6 px even at the right edge of a 1352-px image.
+// the tile's 32x32 block while staging, so the per-pair offset dx = px + 0.5 - u
+// is exact to ~1e-6 px even at the right edge of a 1352-px image.
 #include <hip/hip_runtime.h>
 
 #include "dev_util.h"
@@ -58,8 +58,12 @@ __global__ void __launch_bounds__(TW *TH) composite_kernel(CompArgs a) {
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < a.W && py < a.H;
-    const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
-    const float ox = (float)(tx * TW), oy = (float)(ty * TH);
+    // Offsets are taken from the origin of the enclosing 32x32 block, which is
+    // the same for every tile shape, so a pixel's arithmetic does not depend on
+    // the tiling.
+    const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;
+    const float fx = (float)(px - bx0) + 0.5f, fy = (float)(py - by0) + 0.5f;
+    const float ox = (float)bx0, oy = (float)by0;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const float amin = a.rp.alpha_min, amax = a.rp.alpha_max, tmin = a.rp.t_min;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
@@ -146,8 +150,9 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < a.W && py < a.H;
-    const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
-    const float ox = (float)(tx * TW), oy = (float)(ty * TH);
+    const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;   // as in the forward
+    const float fx = (float)(px - bx0) + 0.5f, fy = (float)(py - by0) + 0.5f;
+    const float ox = (float)bx0, oy = (float)by0;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const float amin = a.rp.alpha_min, amax = a.rp.alpha_max;
     const int64_t pix = (int64_t)py * a.W + px;

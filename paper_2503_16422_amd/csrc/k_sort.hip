@@ -178,27 +178,57 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
     }
 }
 
-// One thread per visible Gaussian (in depth order) writes its tile keys.
-__global__ void duplicate_kernel(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
-                                 const int64_t *n_vis_dev, int64_t n_max, RenderParams rp,
-                                 uint32_t *tile_keys, uint32_t *ids, const int64_t *n_inst_dev,
-                                 int64_t capacity, int32_t *overflow) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= count_of(n_vis_dev, n_max)) return;
-    if (j == 0 && *n_inst_dev > capacity) atomicOr(overflow, 1);
-    const uint32_t id = order[j];
-    const int4 r = reinterpret_cast<const int4 *>(rect)[id];
-    uint64_t off = offsets[j];
-    const int tx0 = r.x / rp.tile_w, tx1 = r.z / rp.tile_w;
-    const int ty0 = r.y / rp.tile_h, ty1 = r.w / rp.tile_h;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            if (off < (uint64_t)capacity) {
-                tile_keys[off] = (uint32_t)(ty * rp.tiles_x + tx);
-                ids[off] = id;
-            }
-            ++off;
+// Tile-key emission, load-balanced over instances.  Block b owns the visible
+// Gaussians at sorted positions [256 b, 256 b + 256) and therefore the
+// instances [off[256 b], off[256 b + 256]).  Its threads walk those instances
+// with a stride of 256 (coalesced writes); each finds its Gaussian by a
+// binary search over the block's offsets in LDS and its tile from the
+// position inside the Gaussian's tile rectangle (row-major), so a Gaussian
+// covering thousands of tiles is spread over the whole block.
+constexpr int kDupNT = 256;
+
+__global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order, const uint64_t *offsets,
+                                                           const int32_t *rect, const int64_t *n_vis_dev,
+                                                           int64_t n_max, RenderParams rp, uint32_t *tile_keys,
+                                                           uint32_t *ids, const int64_t *n_inst_dev,
+                                                           int64_t capacity, int32_t *overflow) {
+    __shared__ uint64_t s_off[kDupNT + 1];
+    __shared__ int32_t s_tx0[kDupNT], s_ty0[kDupNT], s_w[kDupNT];
+    __shared__ uint32_t s_id[kDupNT];
+    const int64_t n_vis = count_of(n_vis_dev, n_max);
+    const int64_t n_inst = *n_inst_dev;
+    const int64_t j0 = (int64_t)blockIdx.x * kDupNT;
+    if (j0 >= n_vis) return;                           // uniform
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_inst > capacity) atomicOr(overflow, 1);
+    const int cnt = (int)min((int64_t)kDupNT, n_vis - j0);
+    const int t = threadIdx.x;
+    if (t < cnt) {
+        const uint32_t id = order[j0 + t];
+        const int4 r = reinterpret_cast<const int4 *>(rect)[id];
+        const int tx0 = r.x / rp.tile_w, tx1 = r.z / rp.tile_w;
+        s_tx0[t] = tx0;
+        s_ty0[t] = r.y / rp.tile_h;
+        s_w[t] = tx1 - tx0 + 1;
+        s_id[t] = id;
+        s_off[t] = offsets[j0 + t];
+    }
+    if (t == 0) s_off[cnt] = (j0 + cnt < n_vis) ? offsets[j0 + cnt] : (uint64_t)n_inst;
+    __syncthreads();
+    const uint64_t first = s_off[0], last = s_off[cnt];
+    const uint64_t cap = (uint64_t)capacity;
+    for (uint64_t e = first + t; e < last && e < cap; e += kDupNT) {
+        int lo = 0, hi = cnt - 1;                      // largest i with s_off[i] <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
         }
+        const uint32_t k = (uint32_t)(e - s_off[lo]);
+        const int w = s_w[lo];
+        const int ty = s_ty0[lo] + (int)(k / (uint32_t)w);
+        const int tx = s_tx0[lo] + (int)(k % (uint32_t)w);
+        tile_keys[e] = (uint32_t)(ty * rp.tiles_x + tx);
+        ids[e] = s_id[lo];
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -283,7 +313,7 @@ hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, cons
                             uint32_t *tile_keys, uint32_t *ids, const int64_t *n_inst_dev,
                             int64_t capacity, int32_t *overflow, hipStream_t s) {
     if (n_max == 0) return hipSuccess;
-    hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, order, offsets,
+    hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_for(n_max, kDupNT)), dim3(kDupNT), 0, s, order, offsets,
                        rect, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
     return hipGetLastError();
 }

@@ -12,7 +12,9 @@ F32 = lambda x: float(np.float32(x))
 IMG_TOL = 1e-4
 # A flagged pixel can differ by at most one near-threshold contribution.
 FLAG_TOL = 2e-2
-MAX_FLAGGED_FRAC = 5e-4
+# Expected flagged fraction: ~(pairs evaluated per pixel) x (2e-5 / ln(255)),
+# e.g. 225 pairs/pixel at 1352x1014 -> ~0.08%.  Allow a few times that.
+MAX_FLAGGED_FRAC = 5e-3
 
 
 def oracle_settings(cfg=None, **kw) -> oc.Settings:
