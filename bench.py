@@ -203,6 +203,74 @@ def fwd_bwd(ctx, steps, warmup):
     return dt * 1e3 / steps, views
 
 
+def batched(ctx, steps=3):
+    """8 scenes of uneven size x 64 timestamps x 4 cameras at 800x800, masked,
+    rendered by one HIP-graph launch; the tile/batch configuration comes from
+    the autotuner run on a 64-view subset."""
+    import numpy as np
+    import torch
+    from paper_2503_16422_amd import _lib, inputs
+    from paper_2503_16422_amd.render import GaussianModel
+    sizes = inputs.batched_scene_sizes()
+    cams = inputs.batch_cameras(800, 800)
+    frames = inputs.frame_times(64)
+    keys = [0, 13, 26, 39, 52, 63]
+    models, masks = [], {}
+    sync()
+    t0 = time.perf_counter()
+    for s, n in enumerate(sizes):
+        m = GaussianModel.from_scene(inputs.long_scene(n, seed=s), "cuda:0")
+        models.append(m)
+        for w in range(len(keys) - 1):
+            lo, hi = keys[w], keys[w + 1]
+            _, idx, cnt = ctx.build_active_mask(m, frames[lo:hi + 1], frames[lo], frames[hi],
+                                                _lib.MASK_TEMPORAL_AND_TILE, cams)
+            masks[(s, w)] = (idx, int(cnt.item()))
+    sync()
+    setup_s = time.perf_counter() - t0
+    win = lambda f: min(np.searchsorted(keys, f, side="right") - 1, len(keys) - 2)
+    views = []
+    for f in range(64):
+        for c in range(4):
+            for s in range(len(sizes)):
+                idx, n = masks[(s, win(f))]
+                views.append((s, cams[c], float(frames[f]), idx, n))
+    per = 128
+    best, sweep = ctx.autotune(models, views[:64], _lib.default_cfg(), views_per_launch=64, repeats=2)
+    cfg = _lib.default_cfg(tile_w=best.tile_w, tile_h=best.tile_h, batch=best.batch,
+                           pixels_per_thread=best.pixels_per_thread)
+    out = torch.empty((len(views), 3, 800, 800), dtype=torch.float32, device="cuda")
+    ctx.profile(True)
+    ctx.render_batch(models, views, cfg, views_per_launch=per, out=out)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    n_launch = (len(views) + per - 1) // per
+    cap = int(prof["instances"] / n_launch * 1.5) + 65536
+    for _ in range(3):
+        cfg.instance_capacity = cap
+        ctx.render_batch(models, views, cfg, views_per_launch=per, use_graph=True, out=out)
+        try:
+            ctx.check_overflow()
+            break
+        except _lib.FdgsError:
+            cap *= 2
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.render_batch(models, views, cfg, views_per_launch=per, use_graph=True, out=out)
+    sync()
+    dt = (time.perf_counter() - t0) / steps
+    ctx.check_overflow()
+    return {"views": len(views), "resolution": [800, 800], "scenes": sizes, "views_per_launch": per,
+            "graph_ms_per_batch": round(dt * 1e3, 2), "views_per_s": round(len(views) / dt, 1),
+            "instances_per_view": int(prof["instances"] / len(views)),
+            "autotuned": {"tile": [best.tile_w, best.tile_h], "batch": best.batch,
+                          "pixels_per_thread": best.pixels_per_thread},
+            "autotune_sweep_ms_64_views": {f"{r['tile'][0]}x{r['tile'][1]}/b{r['batch']}/p{r['pixels_per_thread']}":
+                                           round(r["ms"], 3) for r in sweep},
+            "setup_s": round(setup_s, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +377,12 @@ def main():
                              "kept_mean": int(np.mean(dkept))}
         extra["masked_200k_vs_dense_3M_vanilla"] = round(fps / d_fps, 2)
         del dmodel, dmasks
+        torch.cuda.empty_cache()
+
+        # ---- batched multi-view render (HIP graph + autotuner) ------------------------
+        log("[bench] batched: 8 scenes x 64 t x 4 cameras at 800x800")
+        extra["batched_2048_views"] = batched(ctx)
+        log(f"[bench] batched: {json.dumps(extra['batched_2048_views'])}")
         torch.cuda.empty_cache()
 
         # ---- forward + backward ------------------------------------------------------

@@ -100,6 +100,9 @@ typedef struct {
 typedef struct {
     int32_t tile_w, tile_h;     /* one of 8x8, 16x16, 32x8            [16x16] */
     int32_t batch;              /* Gaussians staged in LDS: 64/128/256   [128] */
+    int32_t pixels_per_thread;  /* 1, 2 or 4 pixels of a column per thread in
+                                   the forward compositor; 8x8 tiles always
+                                   use 1; 0 picks the default              [0] */
     float bg[3];                /* background, added with the final T  [0,0,0] */
     float alpha_min;            /* alpha below this is skipped         [1/255] */
     float alpha_max;            /* alpha clamp                          [0.99] */
@@ -228,6 +231,60 @@ typedef struct {
 
 FDGS_API fdgs_status fdgs_state_binning(fdgs_ctx *ctx, fdgs_state *state, fdgs_binning *out,
                                hipStream_t stream);
+
+/*
+ * (5) Batched forward for many views across scenes of uneven size (a
+ * multi-view workload such as rendering every (camera, timestamp) of several
+ * dynamic scenes).  The views are processed in launches of views_per_launch
+ * views (0: all at once): each launch runs every stage once over the
+ * concatenated (view, Gaussian) space, bins with (view, tile) keys and
+ * blends all views' tiles in one compositor launch.  Results equal
+ * fdgs_render_forward of each view (no state is kept).
+ *   scenes[n_scenes]: models (device pointers as in fdgs_model).
+ *   views[n_views]: host descriptors; every view has the same width/height;
+ *     idx (device) selects a processed subset of its scene (NULL: all) with
+ *     n_idx entries (host count).
+ *   out_rgb: device [n_views][3][H][W].
+ *   use_graph: 1 captures the whole call in a HIP graph on first use (after
+ *     one eager run that sizes every buffer) and replays it while all
+ *     arguments and the views' contents are unchanged; requires
+ *     cfg->instance_capacity > 0 (per launch).  Synchronises `stream` when
+ *     it (re)builds the graph.
+ */
+typedef struct {
+    int32_t scene;
+    fdgs_camera cam;
+    double t;
+    const uint32_t *idx;
+    int64_t n_idx;
+} fdgs_view;
+
+FDGS_API fdgs_status fdgs_render_batch(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_scenes,
+                                       const fdgs_view *views, int32_t n_views,
+                                       const fdgs_render_cfg *cfg, int32_t views_per_launch,
+                                       int32_t use_graph, float *out_rgb, hipStream_t stream);
+
+/*
+ * Autotuner: renders the batch with every tile shape (8x8, 16x16, 32x8), LDS
+ * batch (64, 128, 256) and pixels-per-thread choice (1, 2, 4; 1 only for
+ * 8x8), times each with HIP events (best of `repeats`), checks that every
+ * configuration's images are bit-identical to the first one's, and writes the
+ * fastest into *inout_cfg (other fields are kept).  results (host, may be
+ * NULL) receives up to max_results entries; *n_results the number tried.
+ * Returns FDGS_ERR_STATE if any configuration's images differed.
+ * Synchronises `stream`.
+ */
+typedef struct {
+    int32_t tile_w, tile_h, batch, pixels_per_thread;
+    double ms;
+    int32_t identical;
+} fdgs_tune_result;
+
+FDGS_API fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_scenes,
+                                   const fdgs_view *views, int32_t n_views, int32_t views_per_launch,
+                                   int32_t repeats, fdgs_render_cfg *inout_cfg,
+                                   fdgs_tune_result *results, int32_t max_results, int32_t *n_results,
+                                   hipStream_t stream);
 
 /*
  * Reports FDGS_ERR_CAPACITY if a forward with a fixed instance_capacity on

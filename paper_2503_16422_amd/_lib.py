@@ -24,7 +24,7 @@ MASK_TEMPORAL_AND_TILE = 1
 EXPORTS = ["fdgs_last_error", "fdgs_version", "fdgs_create", "fdgs_destroy", "fdgs_render_cfg_default",
            "fdgs_slice_4d", "fdgs_build_active_mask", "fdgs_render_forward", "fdgs_render_backward",
            "fdgs_state_release", "fdgs_state_binning", "fdgs_check_overflow", "fdgs_profile_enable",
-           "fdgs_profile_read"]
+           "fdgs_profile_read", "fdgs_render_batch", "fdgs_autotune"]
 
 STAGES = ["preprocess", "compact", "depth_sort", "offsets", "duplicate", "tile_sort", "ranges", "composite",
           "bwd_composite", "bwd_preprocess"]
@@ -46,7 +46,7 @@ class Camera(ctypes.Structure):
 
 class RenderCfg(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("bg", ctypes.c_float * 3), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("pixels_per_thread", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float), ("temporal_cull", ctypes.c_int32),
                 ("instance_capacity", ctypes.c_int64)]
 
@@ -67,6 +67,16 @@ class Binning(ctypes.Structure):
                 ("depth", ctypes.c_void_p), ("visible", ctypes.c_void_p), ("n_inst", ctypes.c_int64),
                 ("n_vis", ctypes.c_int64), ("n_proc", ctypes.c_int64), ("n_tiles", ctypes.c_int32),
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_int32), ("cam", Camera), ("t", ctypes.c_double), ("idx", ctypes.c_void_p),
+                ("n_idx", ctypes.c_int64)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("pixels_per_thread", ctypes.c_int32), ("ms", ctypes.c_double), ("identical", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -107,6 +117,9 @@ def load() -> ctypes.CDLL:
     lib.fdgs_check_overflow.argtypes = [VP, VP]
     lib.fdgs_profile_enable.argtypes = [VP, I32]
     lib.fdgs_profile_read.argtypes = [VP, P(Profile), I32]
+    lib.fdgs_render_batch.argtypes = [VP, P(Model), I32, P(View), I32, P(RenderCfg), I32, I32, VP, VP]
+    lib.fdgs_autotune.argtypes = [VP, P(Model), I32, P(View), I32, I32, I32, P(RenderCfg), P(TuneResult), I32,
+                                  P(I32), VP]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:   # default restype: status

@@ -71,6 +71,8 @@ void release(Buf &b) {
     b.cap = 0;
 }
 
+constexpr int32_t kDefaultPpt = 2;
+
 bool valid_tile(int w, int h) { return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8); }
 
 int bits_for(int64_t v) {   // bits needed to represent values in [0, v)
@@ -85,7 +87,7 @@ struct fdgs_state {
     fdgs_ctx *owner = nullptr;
     bool has_forward = false;
     // per processed Gaussian
-    Buf rec, depth_key, rect, tiles, visible, vis_pos, order_k, order_v, order_k2, order_v2, offsets;
+    Buf rec, depth_key, rect, tiles, visible, vis_pos, order_k, order_v, order_k2, order_v2, offsets, view_of;
     // per instance
     Buf tkeys, tids, tkeys2, tids2;
     // per tile / pixel
@@ -109,7 +111,7 @@ struct fdgs_state {
 
     void free_all() {
         for (Buf *b : {&rec, &depth_key, &rect, &tiles, &visible, &vis_pos, &order_k, &order_v, &order_k2,
-                       &order_v2, &offsets, &tkeys, &tids, &tkeys2, &tids2, &ranges, &T_final,
+                       &order_v2, &offsets, &view_of, &tkeys, &tids, &tkeys2, &tids2, &ranges, &T_final,
                        &n_contrib, &counts, &g2d, &scratch})
             release(*b);
     }
@@ -134,6 +136,14 @@ struct fdgs_ctx {
     std::vector<PendingStage> pending;
     double ms[FDGS_NUM_STAGES] = {};
     int64_t calls[FDGS_NUM_STAGES] = {};
+    bool capturing = false;        // inside hipStreamBeginCapture / EndCapture
+    // batched rendering
+    fdgs_state batch_state;
+    std::vector<Buf> batch_tables;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
+    Buf tune_ref, tune_img, tune_diff;
 
     hipEvent_t get_event() {
         if (!free_events.empty()) {
@@ -156,10 +166,10 @@ struct StageTimer {
     hipStream_t s;
     hipEvent_t e0 = nullptr;
     StageTimer(fdgs_ctx *c_, int stage_, hipStream_t s_) : c(c_), stage(stage_), s(s_) {
-        if (c->prof && (e0 = c->get_event())) (void)hipEventRecord(e0, s);
+        if (c->prof && !c->capturing && (e0 = c->get_event())) (void)hipEventRecord(e0, s);
     }
     ~StageTimer() {
-        if (!c->prof || !e0) return;
+        if (!c->prof || c->capturing || !e0) return;
         hipEvent_t e1 = c->get_event();
         if (!e1) return;
         (void)hipEventRecord(e1, s);
@@ -201,6 +211,7 @@ fdgs_status fdgs_create(fdgs_ctx **out, int32_t device) {
     if (!c) return fail(FDGS_ERR_HIP, "fdgs_create: out of host memory");
     c->device = device;
     c->scratch_state.owner = c;
+    c->batch_state.owner = c;
     hipError_t e = ensure(c->overflow, sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(c->overflow.p, 0, sizeof(int32_t));
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_counts, 4 * sizeof(int64_t), hipHostMallocDefault);
@@ -222,6 +233,13 @@ fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
         delete s;
     }
     ctx->scratch_state.free_all();
+    ctx->batch_state.free_all();
+    for (Buf &b : ctx->batch_tables) release(b);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    release(ctx->tune_ref);
+    release(ctx->tune_img);
+    release(ctx->tune_diff);
     release(ctx->overflow);
     release(ctx->mask_frames);
     release(ctx->mask_views);
@@ -276,6 +294,10 @@ fdgs_status check_cfg(const fdgs_render_cfg *cfg, const char *fn) {
                     cfg->tile_h);
     if (cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
         return fail(FDGS_ERR_INVALID_ARG, "%s: batch %d not one of 64, 128, 256", fn, cfg->batch);
+    if (cfg->pixels_per_thread != 0 && cfg->pixels_per_thread != 1 && cfg->pixels_per_thread != 2 &&
+        cfg->pixels_per_thread != 4)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: pixels_per_thread %d not one of 0, 1, 2, 4", fn,
+                    cfg->pixels_per_thread);
     if (!(cfg->alpha_min > 0.0f) || !(cfg->alpha_max > cfg->alpha_min) || !(cfg->alpha_max < 1.0f))
         return fail(FDGS_ERR_INVALID_ARG, "%s: need 0 < alpha_min < alpha_max < 1", fn);
     if (!(cfg->t_min > 0.0f) || !(cfg->t_min < 1.0f))
@@ -388,6 +410,165 @@ fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const
     return FDGS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
+    RenderParams rp;
+    rp.tile_w = cfg->tile_w;
+    rp.tile_h = cfg->tile_h;
+    rp.tiles_x = (W + cfg->tile_w - 1) / cfg->tile_w;
+    rp.tiles_y = (H + cfg->tile_h - 1) / cfg->tile_h;
+    for (int k = 0; k < 3; ++k) rp.bg[k] = cfg->bg[k];
+    rp.alpha_min = cfg->alpha_min;
+    rp.alpha_max = cfg->alpha_max;
+    rp.t_min = cfg->t_min;
+    rp.dilation = cfg->dilation;
+    rp.temporal_cull = cfg->temporal_cull ? 1 : 0;
+    return rp;
+}
+
+// The forward pipeline for V views of one resolution.  V == 1: `one` by value,
+// processed count optionally on the device (n_dev).  V > 1: `table` is a
+// device copy of the views with host-known counts summing to n_total.
+// With capture set nothing may synchronise or allocate: the caller guarantees
+// buffers are already large enough and a fixed instance capacity is given.
+fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const ViewDesc *table, int32_t V,
+                        const int64_t *n_dev, int64_t n_total, int32_t W, int32_t H, const fdgs_render_cfg *cfg,
+                        float *out_rgb, float *out_T, bool need_state, hipStream_t stream) {
+    const char *fn = "fdgs_render";
+    const RenderParams rp = make_params(cfg, W, H);
+    const int64_t tiles_per_view = (int64_t)rp.tiles_x * rp.tiles_y;
+    const int64_t n_keys = tiles_per_view * V;
+    if (n_keys >= (int64_t(1) << 31)) return fail(FDGS_ERR_INVALID_ARG, "%s: too many tiles x views", fn);
+    const int64_t n_max = n_total;
+    const int64_t npx = (int64_t)W * H;
+
+    HIP_TRY(ensure(S->rec, sizeof(Rec2D) * n_max));
+    HIP_TRY(ensure(S->depth_key, sizeof(uint64_t) * n_max));
+    HIP_TRY(ensure(S->rect, sizeof(int32_t) * 4 * n_max));
+    HIP_TRY(ensure(S->tiles, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->visible, n_max));
+    HIP_TRY(ensure(S->vis_pos, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_k, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_v, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_k2, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->order_v2, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->offsets, sizeof(uint64_t) * n_max));
+    if (V > 1) HIP_TRY(ensure(S->view_of, sizeof(uint32_t) * n_max));
+    HIP_TRY(ensure(S->counts, sizeof(int64_t) * 4));
+    HIP_TRY(ensure(S->ranges, sizeof(uint32_t) * 2 * n_keys));
+    if (need_state) {
+        HIP_TRY(ensure(S->T_final, sizeof(float) * npx));
+        HIP_TRY(ensure(S->n_contrib, sizeof(uint32_t) * npx));
+    }
+    const size_t scratch = std::max(scan_scratch_bytes(n_max), sort_scratch_bytes(n_max));
+    HIP_TRY(ensure(S->scratch, scratch));
+    int64_t *counts = S->counts.as<int64_t>();
+    uint32_t *view_of = V > 1 ? S->view_of.as<uint32_t>() : nullptr;
+
+    PreprocOut po{S->rec.as<Rec2D>(), S->depth_key.as<uint64_t>(), S->rect.as<int32_t>(),
+                  S->tiles.as<uint32_t>(), S->visible.as<uint8_t>(), view_of};
+    {
+        StageTimer tm(ctx, FDGS_STAGE_PREPROCESS, stream);
+        HIP_TRY(launch_preprocess(one, table, V, n_dev, n_total, rp, po, stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_COMPACT, stream);
+        HIP_TRY(scan_flags_u8(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(), n_dev, n_max, counts + 0,
+                              S->scratch.p, stream));
+        HIP_TRY(launch_scatter_visible(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(),
+                                       S->depth_key.as<uint64_t>(), n_dev, n_max, S->order_k.as<uint32_t>(),
+                                       S->order_v.as<uint32_t>(), stream));
+    }
+    uint32_t *ov = nullptr;
+    {
+        StageTimer tm(ctx, FDGS_STAGE_DEPTH_SORT, stream);
+        int alt = 0;
+        HIP_TRY(radix_sort_u32(S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->order_k2.as<uint32_t>(),
+                               S->order_v2.as<uint32_t>(), counts + 0, n_max, 0, 32, S->scratch.p, &alt, stream));
+        uint32_t *ok = alt ? S->order_k2.as<uint32_t>() : S->order_k.as<uint32_t>();
+        ov = alt ? S->order_v2.as<uint32_t>() : S->order_v.as<uint32_t>();
+        HIP_TRY(launch_fix_depth_ties(ok, ov, S->depth_key.as<uint64_t>(), counts + 0, n_max,
+                                      ctx->overflow.as<int32_t>(), stream));
+        if (V > 1) {
+            // group by view, keeping the depth order inside each view (stable)
+            uint32_t *kv = alt ? S->order_k.as<uint32_t>() : S->order_k2.as<uint32_t>();
+            uint32_t *vv = alt ? S->order_v.as<uint32_t>() : S->order_v2.as<uint32_t>();
+            HIP_TRY(launch_gather_u32(view_of, ov, ok, counts + 0, n_max, stream));
+            int alt_v = 0;
+            HIP_TRY(radix_sort_u32(ok, ov, kv, vv, counts + 0, n_max, 0, std::max(1, bits_for(V)), S->scratch.p,
+                                   &alt_v, stream));
+            if (alt_v) ov = vv;
+        }
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_OFFSETS, stream);
+        HIP_TRY(scan_u32_to_u64(S->tiles.as<uint32_t>(), ov, S->offsets.as<uint64_t>(), counts + 0, n_max,
+                                counts + 1, S->scratch.p, stream));
+    }
+    int64_t capacity = cfg->instance_capacity;
+    if (capacity == 0) {
+        HIP_TRY(hipMemcpyAsync(ctx->host_counts, counts, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        capacity = ctx->host_counts[1];
+        if (capacity > 0xffffffffll)
+            return fail(FDGS_ERR_CAPACITY, "%s: %lld tile instances exceed 2^32", fn, (long long)capacity);
+    }
+    HIP_TRY(ensure(S->tkeys, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->tids, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->tkeys2, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->tids2, sizeof(uint32_t) * capacity));
+    HIP_TRY(ensure(S->scratch, std::max(scratch, sort_scratch_bytes(capacity))));
+    {
+        StageTimer tm(ctx, FDGS_STAGE_DUPLICATE, stream);
+        HIP_TRY(launch_duplicate(ov, S->offsets.as<uint64_t>(), S->rect.as<int32_t>(), view_of, counts + 0, n_max, rp,
+                                 S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), counts + 1, capacity,
+                                 ctx->overflow.as<int32_t>(), stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_TILE_SORT, stream);
+        int alt2 = 0;
+        HIP_TRY(radix_sort_u32(S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), S->tkeys2.as<uint32_t>(),
+                               S->tids2.as<uint32_t>(), counts + 1, capacity, 0, std::max(1, bits_for(n_keys)),
+                               S->scratch.p, &alt2, stream));
+        S->sorted_keys = alt2 ? S->tkeys2.as<uint32_t>() : S->tkeys.as<uint32_t>();
+        S->sorted_ids = alt2 ? S->tids2.as<uint32_t>() : S->tids.as<uint32_t>();
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_RANGES, stream);
+        HIP_TRY(launch_tile_ranges(S->sorted_keys, counts + 1, capacity, (int32_t)n_keys, S->ranges.as<uint32_t>(),
+                                   stream));
+    }
+    float *T_out = need_state ? S->T_final.as<float>() : out_T;
+    uint64_t *acc = nullptr;
+    if (ctx->prof && !ctx->capturing) {
+        HIP_TRY(ensure(ctx->prof_acc, 4 * sizeof(uint64_t)));
+        acc = ctx->prof_acc.as<uint64_t>();
+        HIP_TRY(launch_accumulate_counts(n_dev, n_total, counts, capacity, acc, stream));
+    }
+    {
+        StageTimer tm(ctx, FDGS_STAGE_COMPOSITE, stream);
+        HIP_TRY(launch_composite(rp, W, H, V, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
+                                 out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
+                                 acc ? acc + 3 : nullptr,
+                                 cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt, stream));
+    }
+    if (need_state && out_T)
+        HIP_TRY(hipMemcpyAsync(out_T, S->T_final.p, sizeof(float) * npx, hipMemcpyDeviceToDevice, stream));
+    S->rp = rp;
+    S->batch = cfg->batch;
+    S->capacity = capacity;
+    S->W = W;
+    S->H = H;
+    return FDGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 fdgs_status fdgs_render_forward(fdgs_ctx *ctx, const fdgs_model *model, const uint32_t *idx,
                                 const int64_t *n_idx_dev, const fdgs_camera *cam, double t,
                                 const fdgs_render_cfg *cfg, float *out_rgb, float *out_T,
@@ -415,137 +596,246 @@ fdgs_status fdgs_render_forward(fdgs_ctx *ctx, const fdgs_model *model, const ui
     }
     HIP_TRY(hipSetDevice(ctx->device));
     S->has_forward = false;
-    const int32_t W = cam->width, H = cam->height;
-    RenderParams rp;
-    rp.tile_w = cfg->tile_w;
-    rp.tile_h = cfg->tile_h;
-    rp.tiles_x = (W + cfg->tile_w - 1) / cfg->tile_w;
-    rp.tiles_y = (H + cfg->tile_h - 1) / cfg->tile_h;
-    for (int k = 0; k < 3; ++k) rp.bg[k] = cfg->bg[k];
-    rp.alpha_min = cfg->alpha_min;
-    rp.alpha_max = cfg->alpha_max;
-    rp.t_min = cfg->t_min;
-    rp.dilation = cfg->dilation;
-    rp.temporal_cull = cfg->temporal_cull ? 1 : 0;
-    const int32_t n_tiles = rp.tiles_x * rp.tiles_y;
-    const int64_t n_max = model->n;
-    const int64_t *n_proc_dev = idx ? n_idx_dev : nullptr;
-    const KModel km = kmodel(model);
-    const KCam kc = kcam(cam);
-    const int64_t npx = (int64_t)W * H;
-
-    // per processed Gaussian buffers
-    HIP_TRY(ensure(S->rec, sizeof(Rec2D) * n_max));
-    HIP_TRY(ensure(S->depth_key, sizeof(uint64_t) * n_max));
-    HIP_TRY(ensure(S->rect, sizeof(int32_t) * 4 * n_max));
-    HIP_TRY(ensure(S->tiles, sizeof(uint32_t) * n_max));
-    HIP_TRY(ensure(S->visible, n_max));
-    HIP_TRY(ensure(S->vis_pos, sizeof(uint32_t) * n_max));
-    HIP_TRY(ensure(S->order_k, sizeof(uint32_t) * n_max));
-    HIP_TRY(ensure(S->order_v, sizeof(uint32_t) * n_max));
-    HIP_TRY(ensure(S->order_k2, sizeof(uint32_t) * n_max));
-    HIP_TRY(ensure(S->order_v2, sizeof(uint32_t) * n_max));
-    HIP_TRY(ensure(S->offsets, sizeof(uint64_t) * n_max));
-    HIP_TRY(ensure(S->counts, sizeof(int64_t) * 4));
-    HIP_TRY(ensure(S->ranges, sizeof(uint32_t) * 2 * n_tiles));
-    HIP_TRY(ensure(S->T_final, sizeof(float) * npx));
-    HIP_TRY(ensure(S->n_contrib, sizeof(uint32_t) * npx));
-    size_t scratch = std::max(scan_scratch_bytes(n_max), sort_scratch_bytes(n_max));
-    HIP_TRY(ensure(S->scratch, scratch));
-    int64_t *counts = S->counts.as<int64_t>();
-
-    PreprocOut po{S->rec.as<Rec2D>(), S->depth_key.as<uint64_t>(), S->rect.as<int32_t>(),
-                  S->tiles.as<uint32_t>(), S->visible.as<uint8_t>()};
-    {
-        StageTimer tm(ctx, FDGS_STAGE_PREPROCESS, stream);
-        HIP_TRY(launch_preprocess(km, idx, n_proc_dev, n_max, kc, t, rp, po, stream));
-    }
-    {
-        StageTimer tm(ctx, FDGS_STAGE_COMPACT, stream);
-        HIP_TRY(scan_flags_u8(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(), n_proc_dev, n_max,
-                              counts + 0, S->scratch.p, stream));
-        HIP_TRY(launch_scatter_visible(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(),
-                                       S->depth_key.as<uint64_t>(), n_proc_dev, n_max, S->order_k.as<uint32_t>(),
-                                       S->order_v.as<uint32_t>(), stream));
-    }
-    int alt = 0;
-    uint32_t *ov = nullptr;
-    {
-        StageTimer tm(ctx, FDGS_STAGE_DEPTH_SORT, stream);
-        HIP_TRY(radix_sort_u32(S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->order_k2.as<uint32_t>(),
-                               S->order_v2.as<uint32_t>(), counts + 0, n_max, 0, 32, S->scratch.p, &alt, stream));
-        uint32_t *ok = alt ? S->order_k2.as<uint32_t>() : S->order_k.as<uint32_t>();
-        ov = alt ? S->order_v2.as<uint32_t>() : S->order_v.as<uint32_t>();
-        HIP_TRY(launch_fix_depth_ties(ok, ov, S->depth_key.as<uint64_t>(), counts + 0, n_max,
-                                      ctx->overflow.as<int32_t>(), stream));
-    }
-    {
-        StageTimer tm(ctx, FDGS_STAGE_OFFSETS, stream);
-        HIP_TRY(scan_u32_to_u64(S->tiles.as<uint32_t>(), ov, S->offsets.as<uint64_t>(), counts + 0, n_max,
-                                counts + 1, S->scratch.p, stream));
-    }
-
-    int64_t capacity = cfg->instance_capacity;
-    if (capacity == 0) {
-        HIP_TRY(hipMemcpyAsync(ctx->host_counts, counts, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        capacity = ctx->host_counts[1];
-        if (capacity > 0xffffffffll)
-            return fail(FDGS_ERR_CAPACITY, "%s: %lld tile instances exceed 2^32", fn, (long long)capacity);
-    }
-    HIP_TRY(ensure(S->tkeys, sizeof(uint32_t) * capacity));
-    HIP_TRY(ensure(S->tids, sizeof(uint32_t) * capacity));
-    HIP_TRY(ensure(S->tkeys2, sizeof(uint32_t) * capacity));
-    HIP_TRY(ensure(S->tids2, sizeof(uint32_t) * capacity));
-    HIP_TRY(ensure(S->scratch, std::max(scratch, sort_scratch_bytes(capacity))));
-    {
-        StageTimer tm(ctx, FDGS_STAGE_DUPLICATE, stream);
-        HIP_TRY(launch_duplicate(ov, S->offsets.as<uint64_t>(), S->rect.as<int32_t>(), counts + 0, n_max, rp,
-                                 S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), counts + 1, capacity,
-                                 ctx->overflow.as<int32_t>(), stream));
-    }
-    {
-        StageTimer tm(ctx, FDGS_STAGE_TILE_SORT, stream);
-        int alt2 = 0;
-        HIP_TRY(radix_sort_u32(S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), S->tkeys2.as<uint32_t>(),
-                               S->tids2.as<uint32_t>(), counts + 1, capacity, 0, std::max(1, bits_for(n_tiles)),
-                               S->scratch.p, &alt2, stream));
-        S->sorted_keys = alt2 ? S->tkeys2.as<uint32_t>() : S->tkeys.as<uint32_t>();
-        S->sorted_ids = alt2 ? S->tids2.as<uint32_t>() : S->tids.as<uint32_t>();
-    }
-    {
-        StageTimer tm(ctx, FDGS_STAGE_RANGES, stream);
-        HIP_TRY(launch_tile_ranges(S->sorted_keys, counts + 1, capacity, n_tiles, S->ranges.as<uint32_t>(), stream));
-    }
-    const bool need_state = keep_state != nullptr;
-    float *T_out = need_state ? S->T_final.as<float>() : out_T;
-    uint64_t *acc = nullptr;
-    if (ctx->prof) {
-        HIP_TRY(ensure(ctx->prof_acc, 4 * sizeof(uint64_t)));
-        acc = ctx->prof_acc.as<uint64_t>();
-        HIP_TRY(launch_accumulate_counts(n_proc_dev, n_max, counts, capacity, acc, stream));
-    }
-    {
-        StageTimer tm(ctx, FDGS_STAGE_COMPOSITE, stream);
-        HIP_TRY(launch_composite(rp, W, H, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
-                                 out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
-                                 acc ? acc + 3 : nullptr, stream));
-    }
-    if (need_state && out_T)
-        HIP_TRY(hipMemcpyAsync(out_T, S->T_final.p, sizeof(float) * npx, hipMemcpyDeviceToDevice, stream));
-
+    ViewDesc one;
+    one.m = kmodel(model);
+    one.cam = kcam(cam);
+    one.t = t;
+    one.idx = idx;
+    one.p_off = 0;
+    one.n_proc = model->n;
+    const int64_t *n_dev = idx ? n_idx_dev : nullptr;
+    if (fdgs_status st = run_forward(ctx, S, &one, nullptr, 1, n_dev, model->n, cam->width, cam->height, cfg,
+                                     out_rgb, out_T, keep_state != nullptr, stream))
+        return st;
     S->model = *model;
     S->idx = idx;
     S->n_idx_dev = n_idx_dev;
-    S->cam = kc;
+    S->cam = one.cam;
     S->t = t;
-    S->rp = rp;
-    S->batch = cfg->batch;
-    S->n_max = n_max;
-    S->capacity = capacity;
-    S->W = W;
-    S->H = H;
+    S->n_max = model->n;
     S->has_forward = true;
+    return FDGS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+fdgs_status check_batch(const fdgs_model *scenes, int32_t n_scenes, const fdgs_view *views, int32_t n_views,
+                        const char *fn) {
+    if (n_scenes < 1 || !scenes) return fail(FDGS_ERR_INVALID_ARG, "%s: need at least one scene", fn);
+    if (n_views < 1 || !views) return fail(FDGS_ERR_INVALID_ARG, "%s: need at least one view", fn);
+    for (int k = 0; k < n_scenes; ++k)
+        if (fdgs_status st = check_model(&scenes[k], fn)) return st;
+    for (int v = 0; v < n_views; ++v) {
+        const fdgs_view &w = views[v];
+        if (w.scene < 0 || w.scene >= n_scenes)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: view %d names scene %d of %d", fn, v, w.scene, n_scenes);
+        if (fdgs_status st = check_camera(&w.cam, fn)) return st;
+        if (w.cam.width != views[0].cam.width || w.cam.height != views[0].cam.height)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: views differ in image size", fn);
+        if (!std::isfinite(w.t)) return fail(FDGS_ERR_INVALID_ARG, "%s: view %d time not finite", fn, v);
+        if (w.idx && (w.n_idx < 0 || w.n_idx > scenes[w.scene].n))
+            return fail(FDGS_ERR_INVALID_ARG, "%s: view %d n_idx out of range", fn, v);
+    }
+    return FDGS_OK;
+}
+
+// Enqueue every launch of a batch (no graph handling).
+fdgs_status enqueue_batch(fdgs_ctx *ctx, const fdgs_model *scenes, const fdgs_view *views, int32_t n_views,
+                          const fdgs_render_cfg *cfg, int32_t per_launch, bool upload, float *out_rgb,
+                          hipStream_t stream) {
+    const int32_t W = views[0].cam.width, H = views[0].cam.height;
+    const int64_t img = 3ll * W * H;
+    const int32_t n_launch = (n_views + per_launch - 1) / per_launch;
+    if (upload && (int32_t)ctx->batch_tables.size() < n_launch) ctx->batch_tables.resize(n_launch);
+    for (int32_t c = 0; c < n_launch; ++c) {
+        const int32_t v0 = c * per_launch, V = std::min(per_launch, n_views - v0);
+        std::vector<ViewDesc> table(V);
+        int64_t off = 0;
+        for (int32_t k = 0; k < V; ++k) {
+            const fdgs_view &w = views[v0 + k];
+            ViewDesc &d = table[k];
+            d.m = kmodel(&scenes[w.scene]);
+            d.cam = kcam(&w.cam);
+            d.t = w.t;
+            d.idx = w.idx;
+            d.n_proc = w.idx ? w.n_idx : scenes[w.scene].n;
+            d.p_off = off;
+            off += d.n_proc;
+        }
+        if (off >= (int64_t(1) << 32))
+            return fail(FDGS_ERR_CAPACITY, "fdgs_render_batch: %lld Gaussians in one launch exceed 2^32",
+                        (long long)off);
+        Buf &tb = ctx->batch_tables[c];
+        if (upload) {
+            HIP_TRY(ensure(tb, sizeof(ViewDesc) * V));
+            HIP_TRY(hipMemcpy(tb.p, table.data(), sizeof(ViewDesc) * V, hipMemcpyHostToDevice));
+        }
+        if (V == 1) {
+            if (fdgs_status st = run_forward(ctx, &ctx->batch_state, &table[0], nullptr, 1, nullptr, off, W, H, cfg,
+                                             out_rgb + v0 * img, nullptr, false, stream))
+                return st;
+        } else {
+            if (fdgs_status st = run_forward(ctx, &ctx->batch_state, nullptr, tb.as<ViewDesc>(), V, nullptr, off, W,
+                                             H, cfg, out_rgb + v0 * img, nullptr, false, stream))
+                return st;
+        }
+    }
+    return FDGS_OK;
+}
+
+// A captured graph holds the addresses of the batch buffers and view tables;
+// any other use of them (which may re-upload or regrow them) retires it.
+void drop_graph(fdgs_ctx *ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+}
+
+template <typename T>
+void append_bytes(std::vector<unsigned char> &k, const T *p, size_t n) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(p);
+    k.insert(k.end(), b, b + sizeof(T) * n);
+}
+
+}  // namespace
+
+extern "C" {
+
+fdgs_status fdgs_render_batch(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_scenes, const fdgs_view *views,
+                              int32_t n_views, const fdgs_render_cfg *cfg, int32_t views_per_launch,
+                              int32_t use_graph, float *out_rgb, hipStream_t stream) {
+    const char *fn = "fdgs_render_batch";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (fdgs_status st = check_batch(scenes, n_scenes, views, n_views, fn)) return st;
+    if (fdgs_status st = check_cfg(cfg, fn)) return st;
+    if (!out_rgb) return fail(FDGS_ERR_INVALID_ARG, "%s: out_rgb is NULL", fn);
+    if (views_per_launch < 0) return fail(FDGS_ERR_INVALID_ARG, "%s: views_per_launch < 0", fn);
+    if (use_graph && cfg->instance_capacity <= 0)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: use_graph needs a fixed instance_capacity", fn);
+    const int32_t per = views_per_launch ? std::min(views_per_launch, n_views) : n_views;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!use_graph) {
+        drop_graph(ctx);
+        return enqueue_batch(ctx, scenes, views, n_views, cfg, per, true, out_rgb, stream);
+    }
+
+    std::vector<unsigned char> key;
+    append_bytes(key, scenes, n_scenes);
+    append_bytes(key, views, n_views);
+    append_bytes(key, cfg, 1);
+    append_bytes(key, &per, 1);
+    append_bytes(key, &out_rgb, 1);
+    if (ctx->graph_exec && key == ctx->graph_key) {
+        HIP_TRY(hipGraphLaunch(ctx->graph_exec, stream));
+        return FDGS_OK;
+    }
+    drop_graph(ctx);
+    // eager run: uploads the view tables and sizes every buffer
+    if (fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, cfg, per, true, out_rgb, stream)) return st;
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, cfg, per, false, out_rgb, stream);
+    ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &g);
+    if (st != FDGS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(FDGS_ERR_HIP, "%s: capture failed: %s", fn, hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(FDGS_ERR_HIP, "%s: graph instantiation failed: %s", fn, hipGetErrorString(e));
+    }
+    ctx->graph = g;
+    ctx->graph_exec = ex;
+    ctx->graph_key = key;
+    HIP_TRY(hipGraphLaunch(ctx->graph_exec, stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_scenes, const fdgs_view *views,
+                          int32_t n_views, int32_t views_per_launch, int32_t repeats, fdgs_render_cfg *inout_cfg,
+                          fdgs_tune_result *results, int32_t max_results, int32_t *n_results, hipStream_t stream) {
+    const char *fn = "fdgs_autotune";
+    if (!ctx || !inout_cfg) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx or cfg is NULL", fn);
+    if (fdgs_status st = check_batch(scenes, n_scenes, views, n_views, fn)) return st;
+    if (fdgs_status st = check_cfg(inout_cfg, fn)) return st;
+    if (repeats < 1) repeats = 1;
+    const int32_t per = views_per_launch > 0 ? std::min(views_per_launch, n_views) : n_views;
+    HIP_TRY(hipSetDevice(ctx->device));
+    drop_graph(ctx);
+    const size_t img_bytes = sizeof(float) * 3ull * views[0].cam.width * views[0].cam.height * n_views;
+    HIP_TRY(ensure(ctx->tune_ref, img_bytes));
+    HIP_TRY(ensure(ctx->tune_img, img_bytes));
+    HIP_TRY(ensure(ctx->tune_diff, sizeof(unsigned long long)));
+    struct Cand { int tw, th, b, ppt; };
+    std::vector<Cand> cands;
+    const int shapes[3][2] = {{16, 16}, {8, 8}, {32, 8}};
+    for (auto &sh : shapes)
+        for (int b : {64, 128, 256})
+            for (int ppt : {1, 2, 4})
+                if (sh[0] * sh[1] > 64 || ppt == 1) cands.push_back({sh[0], sh[1], b, ppt});
+    hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
+    if (!e0 || !e1) return fail(FDGS_ERR_HIP, "%s: event creation failed", fn);
+    double best = 1e300;
+    int best_i = -1;
+    bool all_same = true;
+    int32_t tried = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        fdgs_render_cfg c = *inout_cfg;
+        c.tile_w = cands[i].tw;
+        c.tile_h = cands[i].th;
+        c.batch = cands[i].b;
+        c.pixels_per_thread = cands[i].ppt;
+        c.instance_capacity = 0;   // exact sizing: tile counts change with the tile shape
+        float *dst = (i == 0 ? ctx->tune_ref : ctx->tune_img).as<float>();
+        if (fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, &c, per, true, dst, stream)) return st;
+        double ms_best = 1e300;
+        for (int r = 0; r < repeats; ++r) {
+            HIP_TRY(hipEventRecord(e0, stream));
+            if (fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, &c, per, false, dst, stream)) return st;
+            HIP_TRY(hipEventRecord(e1, stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            ms_best = std::min(ms_best, (double)ms);
+        }
+        bool same = true;
+        if (i > 0) {
+            unsigned long long diff = 0;
+            HIP_TRY(launch_count_diff(ctx->tune_ref.as<uint32_t>(), ctx->tune_img.as<uint32_t>(),
+                                      (int64_t)(img_bytes / 4), ctx->tune_diff.as<unsigned long long>(), stream));
+            HIP_TRY(hipMemcpyAsync(&diff, ctx->tune_diff.p, sizeof diff, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            same = diff == 0;
+        }
+        all_same = all_same && same;
+        if (results && tried < max_results)
+            results[tried] = fdgs_tune_result{c.tile_w, c.tile_h, c.batch, c.pixels_per_thread, ms_best, same ? 1 : 0};
+        ++tried;
+        if (same && ms_best < best) {
+            best = ms_best;
+            best_i = (int)i;
+        }
+    }
+    ctx->free_events.push_back(e0);
+    ctx->free_events.push_back(e1);
+    if (n_results) *n_results = tried;
+    if (best_i >= 0) {
+        inout_cfg->tile_w = cands[best_i].tw;
+        inout_cfg->tile_h = cands[best_i].th;
+        inout_cfg->batch = cands[best_i].b;
+        inout_cfg->pixels_per_thread = cands[best_i].ppt;
+    }
+    if (!all_same) return fail(FDGS_ERR_STATE, "%s: a configuration rendered different images", fn);
     return FDGS_OK;
 }
 

@@ -42,16 +42,29 @@ struct RenderParams {
 hipError_t launch_slice(const KModel &m, double t, const uint32_t *idx, int64_t count,
                         float *mean3, float *cov3, float *p, hipStream_t s);
 
+// One (scene, camera, time) view of a forward pass.  Its processed entries
+// occupy [p_off, p_off + n_proc) of the concatenated per-Gaussian buffers.
+struct ViewDesc {
+    KModel m;
+    KCam cam;
+    double t;
+    const uint32_t *idx;   // processed subset of the scene, or null for all
+    int64_t p_off;
+    int64_t n_proc;
+};
+
 struct PreprocOut {
     Rec2D *rec;          // [P]
     uint64_t *depth_key; // [P] float64 bits of z
     int32_t *rect;       // [P][4]
     uint32_t *tiles;     // [P] tiles touched (0 = not visible)
     uint8_t *visible;    // [P]
+    uint32_t *view_of;   // [P] view of each entry (written when V > 1)
 };
-hipError_t launch_preprocess(const KModel &m, const uint32_t *idx, const int64_t *n_dev,
-                             int64_t n_max, const KCam &cam, double t, const RenderParams &rp,
-                             const PreprocOut &out, hipStream_t s);
+// V == 1: `one` is passed by value and n_dev may hold the device count.
+// V > 1: `table` is a device array of V views with host-known counts.
+hipError_t launch_preprocess(const ViewDesc *one, const ViewDesc *table, int32_t V, const int64_t *n_dev,
+                             int64_t n_total, const RenderParams &rp, const PreprocOut &out, hipStream_t s);
 
 struct MaskArgs {
     const double *frames;   // device [n_frames]
@@ -90,23 +103,32 @@ hipError_t launch_scatter_visible(const uint8_t *visible, const uint32_t *pos,
 // flag |= 2 when a run of equal float32 depths is too long to reorder.
 hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_t *depth_key,
                                  const int64_t *n_vis_dev, int64_t n_max, int32_t *flag, hipStream_t s);
+// Tile key = view * tiles_per_view + ty * tiles_x + tx (view_of null: view 0).
 hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
-                            const int64_t *n_vis_dev, int64_t n_max, const RenderParams &rp,
-                            uint32_t *tile_keys, uint32_t *ids, const int64_t *n_inst_dev,
-                            int64_t capacity, int32_t *overflow, hipStream_t s);
+                            const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
+                            const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,
+                            const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, hipStream_t s);
+// dst[j] = src[idx[j]] for j < count.
+hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, const int64_t *n_dev,
+                             int64_t n_max, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
                               int32_t n_tiles, uint32_t *ranges, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+// *out = number of 32-bit words where a and b differ.
+hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, int64_t n, unsigned long long *out,
+                             hipStream_t s);
 // Profiling: acc[0..2] += processed, visible, instances (instances clamped to capacity).
 hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
                                     int64_t capacity, uint64_t *acc, hipStream_t s);
 
 // Compositing.  pair_counter (optional) accumulates evaluated (pixel, Gaussian) pairs.
-hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+// V views of W x H share one tile grid: block b renders tile b % n_tiles of
+// view b / n_tiles; view v writes out_rgb + v*3*W*H (out_T, n_contrib: + v*W*H).
+hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
                             const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
-                            uint64_t *pair_counter, hipStream_t s);
+                            uint64_t *pair_counter, int32_t pixels_per_thread, hipStream_t s);
 
 // Backward.
 hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,

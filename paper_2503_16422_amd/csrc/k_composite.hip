@@ -29,10 +29,18 @@ __device__ __forceinline__ float4 staged_conic(const Rec2D &r) {
     return make_float4(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y, -0.5f * kLog2e * r.b.z, r.b.w);
 }
 
-// Base-2 exponent of the 2D Gaussian at offset (dx, dy).  Forward and adjoint
-// call this same function so that both take identical alpha decisions.
+// Base-2 exponent of the 2D Gaussian at offset (dx, dy):
+//   e = (ka dx) dx + dy (kb dx + kc dy).
+// The dx-only terms are computed once per column when a thread owns several
+// pixels of one column; every kernel evaluates exactly this expression, so
+// forward, adjoint and all tile shapes take identical alpha decisions.
+__device__ __forceinline__ float exp2_col_a(float4 q, float dx) { return (q.x * dx) * dx; }
+__device__ __forceinline__ float exp2_col_b(float4 q, float dx) { return q.y * dx; }
+__device__ __forceinline__ float exp2_at(float4 q, float A, float B, float dy) {
+    return fmaf(dy, fmaf(q.z, dy, B), A);
+}
 __device__ __forceinline__ float gauss_exp2(float4 q, float dx, float dy) {
-    return fmaf(dx, fmaf(q.x, dx, q.y * dy), (q.z * dy) * dy);
+    return exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), dy);
 }
 
 struct CompArgs {
@@ -45,76 +53,114 @@ struct CompArgs {
     float *out_T;
     uint32_t *n_contrib;
     unsigned long long *pairs;   // optional counter of evaluated pairs
+    int32_t ppt;                 // pixels per thread (host-side dispatch only)
+    int32_t V;                   // views sharing the launch
 };
 
-template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW *TH) composite_kernel(CompArgs a) {
-    constexpr int NT = TW * TH;
-    __shared__ float2 s_xy[BATCH];
-    __shared__ float4 s_cn[BATCH];    // base-2 exponent coefficients, opacity
-    __shared__ float4 s_rgb[BATCH];
-    const int tile = blockIdx.x;
+// Thread layout: PPT consecutive pixels of one column per thread
+// (TW x TH / PPT threads); the column's dx terms and the LDS reads of a record
+// are shared by the thread's PPT pixels.
+template <int TW, int TH, int BATCH, int PPT>
+__global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
+    constexpr int NT = TW * TH / PPT;
+    static_assert(NT % 64 == 0, "whole wavefronts per tile");
+    __shared__ float4 s_g[BATCH];    // centre (block-relative), ka, kb
+    __shared__ float4 s_h[BATCH];    // kc, opacity, r, g
+    __shared__ float s_b[BATCH];     // b
+    const int n_tiles = a.rp.tiles_x * a.rp.tiles_y;
+    const int view = blockIdx.x / n_tiles;
+    const int tile = blockIdx.x - view * n_tiles;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool inside = px < a.W && py < a.H;
+    const int lx = threadIdx.x % TW, ly0 = (threadIdx.x / TW) * PPT;
+    const int px = tx * TW + lx, py0 = ty * TH + ly0;
     // Offsets are taken from the origin of the enclosing 32x32 block, which is
     // the same for every tile shape, so a pixel's arithmetic does not depend on
     // the tiling.
     const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;
-    const float fx = (float)(px - bx0) + 0.5f, fy = (float)(py - by0) + 0.5f;
+    const float fx = (float)(px - bx0) + 0.5f;
     const float ox = (float)bx0, oy = (float)by0;
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t start = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
     const float amin = a.rp.alpha_min, amax = a.rp.alpha_max, tmin = a.rp.t_min;
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t last = 0, evaluated = 0;
-    bool done = !inside;
+    float fy[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    uint32_t last[PPT], stop[PPT];
+    bool done[PPT];
+    bool all_done = true;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        fy[p] = (float)(py0 + p - by0) + 0.5f;
+        T[p] = 1.0f;
+        C0[p] = C1[p] = C2[p] = 0.0f;
+        last[p] = 0;
+        stop[p] = end - start;
+        done[p] = !(px < a.W && py0 + p < a.H);
+        all_done = all_done && done[p];
+    }
     for (uint32_t base = start; base < end; base += BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
+        if (__syncthreads_count(!all_done) == 0) break;
         const int cnt = (int)min((uint32_t)BATCH, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) {
             const Rec2D r = a.rec[a.ids[base + k]];
-            s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
-            s_cn[k] = staged_conic(r);
-            s_rgb[k] = r.c;
+            const float4 q = staged_conic(r);
+            s_g[k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
+            s_h[k] = make_float4(q.z, q.w, r.c.x, r.c.y);
+            s_b[k] = r.c.z;
         }
         __syncthreads();
-        if (!done) {
-            int k = 0;
-            for (; k < cnt; ++k) {
-                const float2 c = s_xy[k];
-                const float4 q = s_cn[k];
-                const float dx = fx - c.x, dy = fy - c.y;
-                const float alpha = fminf(amax, q.w * __builtin_amdgcn_exp2f(gauss_exp2(q, dx, dy)));
-                if (alpha < amin) continue;
-                const float test = T * (1.0f - alpha);
-                if (test < tmin) {
-                    done = true;
+        if (!all_done) {
+            for (int k = 0; k < cnt; ++k) {
+                const float4 g = s_g[k];
+                const float4 h = s_h[k];
+                const float4 q = make_float4(g.z, g.w, h.x, h.y);
+                const float dx = fx - g.x;
+                const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
+                bool any_left = false;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    if (done[p]) continue;
+                    const float e = exp2_at(q, A, B, fy[p] - g.y);
+                    const float alpha = fminf(amax, q.w * __builtin_amdgcn_exp2f(e));
+                    if (alpha >= amin) {
+                        const float test = T[p] * (1.0f - alpha);
+                        if (test < tmin) {
+                            done[p] = true;
+                            stop[p] = base + k - start + 1;
+                            continue;
+                        }
+                        const float w = alpha * T[p];
+                        C0[p] += h.z * w;
+                        C1[p] += h.w * w;
+                        C2[p] += s_b[k] * w;
+                        T[p] = test;
+                        last[p] = base + k - start + 1;
+                    }
+                    any_left = true;
+                }
+                if (!any_left) {
+                    all_done = true;
                     break;
                 }
-                const float w = alpha * T;
-                const float4 col = s_rgb[k];
-                C0 += col.x * w;
-                C1 += col.y * w;
-                C2 += col.z * w;
-                T = test;
-                last = base + k - start + 1;
             }
-            evaluated += (uint32_t)min(k + 1, cnt);
+        }
+    }
+    const int64_t plane = (int64_t)a.W * a.H;
+    float *out_rgb = a.out_rgb + (int64_t)view * 3 * plane;
+    uint32_t evaluated = 0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int py = py0 + p;
+        if (px < a.W && py < a.H) {
+            const int64_t pix = (int64_t)py * a.W + px;
+            out_rgb[pix] = C0[p] + T[p] * a.rp.bg[0];
+            out_rgb[plane + pix] = C1[p] + T[p] * a.rp.bg[1];
+            out_rgb[2 * plane + pix] = C2[p] + T[p] * a.rp.bg[2];
+            if (a.out_T) a.out_T[view * plane + pix] = T[p];
+            if (a.n_contrib) a.n_contrib[view * plane + pix] = last[p];
+            evaluated += stop[p];
         }
     }
     if (a.pairs) {
         const unsigned long long w = wave_sum((unsigned long long)evaluated);
         if (lane_id() == 0) atomicAdd(a.pairs, w);
-    }
-    if (inside) {
-        const int64_t pix = (int64_t)py * a.W + px;
-        const int64_t plane = (int64_t)a.W * a.H;
-        a.out_rgb[pix] = C0 + T * a.rp.bg[0];
-        a.out_rgb[plane + pix] = C1 + T * a.rp.bg[1];
-        a.out_rgb[2 * plane + pix] = C2 + T * a.rp.bg[2];
-        if (a.out_T) a.out_T[pix] = T;
-        if (a.n_contrib) a.n_contrib[pix] = last;
     }
 }
 
@@ -254,9 +300,22 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
     }
 }
 
+template <int TW, int TH, int BATCH, int PPT>
+void launch_fwd_ppt(const CompArgs &a, int n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
+}
+
+// Pixels per thread: 1 for 8x8 tiles (one wavefront per tile), a.ppt (1, 2
+// or 4) for the 256-pixel tiles.
 template <int TW, int TH, int BATCH>
 void launch_fwd(const CompArgs &a, int n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, s, a);
+    if constexpr (TW * TH == 64) {
+        launch_fwd_ppt<TW, TH, BATCH, 1>(a, n_tiles, s);
+    } else {
+        if (a.ppt == 1) launch_fwd_ppt<TW, TH, BATCH, 1>(a, n_tiles, s);
+        else if (a.ppt == 2) launch_fwd_ppt<TW, TH, BATCH, 2>(a, n_tiles, s);
+        else launch_fwd_ppt<TW, TH, BATCH, 4>(a, n_tiles, s);
+    }
 }
 
 template <int TW, int TH, int BATCH>
@@ -291,13 +350,14 @@ void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
         if (!ok) return hipErrorInvalidValue;                                                   \
     } while (0)
 
-hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
                             const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
-                            uint64_t *pair_counter, hipStream_t s) {
+                            uint64_t *pair_counter, int32_t ppt, hipStream_t s) {
+    if (ppt != 1 && ppt != 2 && ppt != 4) return hipErrorInvalidValue;
     CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, n_contrib,
-               reinterpret_cast<unsigned long long *>(pair_counter)};
-    const int n_tiles = rp.tiles_x * rp.tiles_y;
+               reinterpret_cast<unsigned long long *>(pair_counter), ppt, V};
+    const int n_tiles = rp.tiles_x * rp.tiles_y * V;
     FDGS_DISPATCH(launch_fwd, a);
     return hipGetLastError();
 }

@@ -40,34 +40,32 @@ __global__ void __launch_bounds__(kBlock) slice_kernel(KModel m, double t, const
 }
 
 struct PreArgs {
-    KModel m;
-    const uint32_t *idx;
-    const int64_t *n_dev;
-    int64_t n_max;
-    KCam cam;
-    double t;
+    ViewDesc one;              // the view when V == 1
+    const ViewDesc *table;     // device table when V > 1
+    int32_t V;
+    const int64_t *n_dev;      // device processed count (V == 1 only)
+    int64_t n_total;           // processed entries over all views (upper bound when n_dev)
     RenderParams rp;
     double vanilla_level;
     PreprocOut out;
 };
 
-__global__ void __launch_bounds__(kBlock) preprocess_kernel(PreArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t P = a.n_dev ? min(*a.n_dev, a.n_max) : a.n_max;
-    if (i >= P) return;
-    const int64_t g = a.idx ? (int64_t)a.idx[i] : i;
+// Processed entry j of view vd (local position i = j - vd.p_off).
+__device__ __forceinline__ void preprocess_one(const ViewDesc &vd, int64_t j, const PreArgs &a) {
+    const int64_t i = j - vd.p_off;
+    const int64_t g = vd.idx ? (int64_t)vd.idx[i] : i;
     Gauss4 G;
-    bool vis = load_gaussian(a.m, g, G);
+    bool vis = load_gaussian(vd.m, g, G);
     Sliced S = {};
     Projected Pr = {};
     double opac = 0.0;
     PixRect r = {0, 0, -1, -1};
     if (vis) {
-        S = slice_gaussian(G, a.t);
+        S = slice_gaussian(G, vd.t);
         vis = S.ok;
     }
     if (vis) {
-        Pr = project(a.cam, S, (double)a.rp.dilation);
+        Pr = project(vd.cam, S, (double)a.rp.dilation);
         vis = Pr.ok;
     }
     if (vis) {
@@ -77,7 +75,7 @@ __global__ void __launch_bounds__(kBlock) preprocess_kernel(PreArgs a) {
     }
     if (vis) {
         const double q = cut_level(opac, (double)a.rp.alpha_min, a.rp.temporal_cull, a.vanilla_level);
-        r = pixel_rect(Pr, q, a.cam.W, a.cam.H);
+        r = pixel_rect(Pr, q, vd.cam.W, vd.cam.H);
         vis = r.x0 <= r.x1 && r.y0 <= r.y1;
     }
     uint32_t tiles = 0;
@@ -88,26 +86,43 @@ __global__ void __launch_bounds__(kBlock) preprocess_kernel(PreArgs a) {
         const double det = Pr.c00 * Pr.c11 - Pr.c01 * Pr.c01;
         const double ca = Pr.c11 / det, cb = -Pr.c01 / det, cc = Pr.c00 / det;
         // view direction from the camera centre C = -R^T t to the conditional mean
-        const double *R = a.cam.R;
+        const double *R = vd.cam.R;
         double d[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            d[k] = S.mean3[k] + (R[k] * a.cam.t[0] + R[3 + k] * a.cam.t[1] + R[6 + k] * a.cam.t[2]);
+            d[k] = S.mean3[k] + (R[k] * vd.cam.t[0] + R[3 + k] * vd.cam.t[1] + R[6 + k] * vd.cam.t[2]);
         const double il = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         float rgb[3];
-        sh_to_rgb(a.m.sh, a.m.n, g, a.m.sh_degree, (float)(d[0] * il), (float)(d[1] * il),
+        sh_to_rgb(vd.m.sh, vd.m.n, g, vd.m.sh_degree, (float)(d[0] * il), (float)(d[1] * il),
                   (float)(d[2] * il), rgb);
         const float uh = (float)Pr.u, vh = (float)Pr.v;
         Rec2D rec;
         rec.a = make_float4(uh, vh, (float)(Pr.u - (double)uh), (float)(Pr.v - (double)vh));
         rec.b = make_float4((float)ca, (float)cb, (float)cc, (float)opac);
         rec.c = make_float4(rgb[0], rgb[1], rgb[2], (float)Pr.z);
-        a.out.rec[i] = rec;
-        a.out.depth_key[i] = (uint64_t)__double_as_longlong(Pr.z);
-        reinterpret_cast<int4 *>(a.out.rect)[i] = make_int4(r.x0, r.y0, r.x1, r.y1);
+        a.out.rec[j] = rec;
+        a.out.depth_key[j] = (uint64_t)__double_as_longlong(Pr.z);
+        reinterpret_cast<int4 *>(a.out.rect)[j] = make_int4(r.x0, r.y0, r.x1, r.y1);
     }
-    a.out.tiles[i] = tiles;
-    a.out.visible[i] = vis ? 1 : 0;
+    a.out.tiles[j] = tiles;
+    a.out.visible[j] = vis ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) preprocess_kernel(PreArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t P = (a.V == 1 && a.n_dev) ? min(*a.n_dev, a.n_total) : a.n_total;
+    if (j >= P) return;
+    if (a.V == 1) {
+        preprocess_one(a.one, j, a);
+        return;
+    }
+    int lo = 0, hi = a.V - 1;             // last view whose range starts at or before j
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.table[mid].p_off <= j) lo = mid; else hi = mid - 1;
+    }
+    a.out.view_of[j] = (uint32_t)lo;
+    preprocess_one(a.table[lo], j, a);
 }
 
 struct MaskKArgs {
@@ -161,21 +176,19 @@ hipError_t launch_slice(const KModel &m, double t, const uint32_t *idx, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const KModel &m, const uint32_t *idx, const int64_t *n_dev,
-                             int64_t n_max, const KCam &cam, double t, const RenderParams &rp,
-                             const PreprocOut &out, hipStream_t s) {
-    if (n_max == 0) return hipSuccess;
+hipError_t launch_preprocess(const ViewDesc *one, const ViewDesc *table, int32_t V, const int64_t *n_dev,
+                             int64_t n_total, const RenderParams &rp, const PreprocOut &out, hipStream_t s) {
+    if (n_total == 0) return hipSuccess;
     PreArgs a;
-    a.m = m;
-    a.idx = idx;
+    a.one = one ? *one : ViewDesc{};
+    a.table = table;
+    a.V = V;
     a.n_dev = n_dev;
-    a.n_max = n_max;
-    a.cam = cam;
-    a.t = t;
+    a.n_total = n_total;
     a.rp = rp;
     a.vanilla_level = 2.0 * log(1.0 / (double)rp.alpha_min) * (1.0 + 1e-4) + 1e-4;
     a.out = out;
-    const unsigned grid = (unsigned)((n_max + kBlock - 1) / kBlock);
+    const unsigned grid = (unsigned)((n_total + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }

@@ -188,13 +188,14 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
 constexpr int kDupNT = 256;
 
 __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order, const uint64_t *offsets,
-                                                           const int32_t *rect, const int64_t *n_vis_dev,
-                                                           int64_t n_max, RenderParams rp, uint32_t *tile_keys,
-                                                           uint32_t *ids, const int64_t *n_inst_dev,
-                                                           int64_t capacity, int32_t *overflow) {
+                                                           const int32_t *rect, const uint32_t *view_of,
+                                                           const int64_t *n_vis_dev, int64_t n_max, RenderParams rp,
+                                                           uint32_t *tile_keys, uint32_t *ids,
+                                                           const int64_t *n_inst_dev, int64_t capacity,
+                                                           int32_t *overflow) {
     __shared__ uint64_t s_off[kDupNT + 1];
     __shared__ int32_t s_tx0[kDupNT], s_ty0[kDupNT], s_w[kDupNT];
-    __shared__ uint32_t s_id[kDupNT];
+    __shared__ uint32_t s_id[kDupNT], s_base[kDupNT];
     const int64_t n_vis = count_of(n_vis_dev, n_max);
     const int64_t n_inst = *n_inst_dev;
     const int64_t j0 = (int64_t)blockIdx.x * kDupNT;
@@ -210,6 +211,8 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
         s_ty0[t] = r.y / rp.tile_h;
         s_w[t] = tx1 - tx0 + 1;
         s_id[t] = id;
+        // tile keys of view v start at v * tiles per view
+        s_base[t] = view_of ? view_of[id] * (uint32_t)(rp.tiles_x * rp.tiles_y) : 0u;
         s_off[t] = offsets[j0 + t];
     }
     if (t == 0) s_off[cnt] = (j0 + cnt < n_vis) ? offsets[j0 + cnt] : (uint64_t)n_inst;
@@ -226,9 +229,22 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
         const int w = s_w[lo];
         const int ty = s_ty0[lo] + (int)(k / (uint32_t)w);
         const int tx = s_tx0[lo] + (int)(k % (uint32_t)w);
-        tile_keys[e] = (uint32_t)(ty * rp.tiles_x + tx);
+        tile_keys[e] = s_base[lo] + (uint32_t)(ty * rp.tiles_x + tx);
         ids[e] = s_id[lo];
     }
+}
+
+__global__ void gather_u32_kernel(const uint32_t *src, const uint32_t *idx, uint32_t *dst,
+                                  const int64_t *n_dev, int64_t n_max) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < count_of(n_dev, n_max)) dst[j] = src[idx[j]];
+}
+
+__global__ void count_diff_kernel(const uint32_t *a, const uint32_t *b, int64_t n, unsigned long long *out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool d = j < n && a[j] != b[j];
+    const unsigned long long c = __popcll(__ballot(d));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -309,12 +325,27 @@ hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_
 }
 
 hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
-                            const int64_t *n_vis_dev, int64_t n_max, const RenderParams &rp,
-                            uint32_t *tile_keys, uint32_t *ids, const int64_t *n_inst_dev,
-                            int64_t capacity, int32_t *overflow, hipStream_t s) {
+                            const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
+                            const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,
+                            const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, hipStream_t s) {
     if (n_max == 0) return hipSuccess;
     hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_for(n_max, kDupNT)), dim3(kDupNT), 0, s, order, offsets,
-                       rect, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
+                       rect, view_of, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, const int64_t *n_dev,
+                             int64_t n_max, hipStream_t s) {
+    if (n_max > 0)
+        hipLaunchKernelGGL(gather_u32_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, src, idx, dst, n_dev,
+                           n_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, int64_t n, unsigned long long *out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(out), (int64_t)2, 0u);
+    if (n > 0) hipLaunchKernelGGL(count_diff_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, b, n, out);
     return hipGetLastError();
 }
 

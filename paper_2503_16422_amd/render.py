@@ -211,6 +211,53 @@ class Context:
                    tiles_x=b.tiles_x, tiles_y=b.tiles_y)
         return out
 
+    # (5) ------------------------------------------------------------------
+    @staticmethod
+    def _batch_structs(scenes, views):
+        ms = (_lib.Model * len(scenes))(*[m.struct() for m in scenes])
+        vs = (_lib.View * len(views))()
+        for k, v in enumerate(views):
+            scene, cam, t = v[0], v[1], v[2]
+            idx = v[3] if len(v) > 3 else None
+            n_idx = v[4] if len(v) > 4 else (int(idx.numel()) if idx is not None else 0)
+            vs[k].scene = int(scene)
+            vs[k].cam = _lib.camera_struct(cam)
+            vs[k].t = float(t)
+            vs[k].idx = idx.data_ptr() if idx is not None else None
+            vs[k].n_idx = int(n_idx)
+        return ms, vs
+
+    def render_batch(self, scenes, views, cfg: Optional[_lib.RenderCfg] = None, views_per_launch: int = 0,
+                     use_graph: bool = False, out: Optional[torch.Tensor] = None):
+        """views: sequence of (scene index, camera, t[, idx tensor[, n_idx]]).  Returns [V, 3, H, W]."""
+        cfg = cfg if cfg is not None else _lib.default_cfg()
+        ms, vs = self._batch_structs(scenes, views)
+        H, W = vs[0].cam.height, vs[0].cam.width
+        if out is None:
+            out = torch.empty((len(views), 3, H, W), dtype=torch.float32, device=self.device)
+        _lib.check(self.lib.fdgs_render_batch(self.handle, ms, len(scenes), vs, len(views), ctypes.byref(cfg),
+                                              int(views_per_launch), 1 if use_graph else 0, _ptr(out),
+                                              _stream(self.device)))
+        self._keep = (ms, vs)
+        return out
+
+    def autotune(self, scenes, views, cfg: Optional[_lib.RenderCfg] = None, views_per_launch: int = 0,
+                 repeats: int = 3):
+        """Returns (best cfg, list of per-configuration results)."""
+        cfg = _lib.default_cfg() if cfg is None else cfg
+        best = _lib.RenderCfg()
+        ctypes.memmove(ctypes.byref(best), ctypes.byref(cfg), ctypes.sizeof(cfg))
+        ms, vs = self._batch_structs(scenes, views)
+        res = (_lib.TuneResult * 32)()
+        n = ctypes.c_int32()
+        status = self.lib.fdgs_autotune(self.handle, ms, len(scenes), vs, len(views), int(views_per_launch),
+                                        int(repeats), ctypes.byref(best), res, 32, ctypes.byref(n),
+                                        _stream(self.device))
+        out = [dict(tile=(r.tile_w, r.tile_h), batch=r.batch, pixels_per_thread=r.pixels_per_thread, ms=r.ms,
+                    identical=bool(r.identical)) for r in res[: n.value]]
+        _lib.check(status)
+        return best, out
+
     def check_overflow(self):
         _lib.check(self.lib.fdgs_check_overflow(self.handle, _stream(self.device)))
 

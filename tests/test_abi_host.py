@@ -61,5 +61,5 @@ def test_struct_layouts_match_header():
     # sizes follow the C layout rules for the declared members
     assert ctypes.sizeof(_lib.Model) == 6 * 8 + 8 + 8
     assert ctypes.sizeof(_lib.Camera) == 9 * 8 + 3 * 8 + 5 * 8 + 2 * 4
-    assert ctypes.sizeof(_lib.RenderCfg) == 3 * 4 + 3 * 4 + 4 * 4 + 4 + 4 + 8
+    assert ctypes.sizeof(_lib.RenderCfg) == 4 * 4 + 3 * 4 + 4 * 4 + 4 + 8
     assert ctypes.sizeof(_lib.Grads) == 6 * 8

@@ -1,0 +1,107 @@
+"""Batched multi-view rendering, its HIP-graph replay and the autotuner."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import composite as oc
+from paper_2503_16422_amd import _lib, inputs
+from tests.gpu_helpers import compare_image, oracle_settings
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2503_16422_amd.render import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def batch_setup(ctx):
+    from paper_2503_16422_amd.render import GaussianModel
+    sizes = [2000, 5000, 9000]
+    scenes = [inputs.long_scene(n, seed=s) for s, n in enumerate(sizes)]
+    models = [GaussianModel.from_scene(sc, "cuda:0") for sc in scenes]
+    cams = inputs.batch_cameras(120, 96)
+    frames = inputs.frame_times(64)
+    views = []
+    masks = {}
+    rng = np.random.default_rng(0)
+    for k in range(11):
+        s = int(rng.integers(0, 3))
+        c = int(rng.integers(0, 4))
+        f = int(rng.integers(0, 64))
+        if k % 3 == 0:       # a masked view: active set of the window around f
+            lo, hi = max(0, f - 6), min(63, f + 6)
+            if (s, lo) not in masks:
+                _, idx, cnt = ctx.build_active_mask(models[s], frames[lo:hi + 1], frames[lo], frames[hi],
+                                                    _lib.MASK_TEMPORAL)
+                masks[(s, lo)] = (idx, int(cnt.item()))
+            idx, n = masks[(s, lo)]
+            views.append((s, cams[c], float(frames[f]), idx, n))
+        else:
+            views.append((s, cams[c], float(frames[f])))
+    return scenes, models, views
+
+
+def single(ctx, models, v, cfg):
+    if len(v) > 3:
+        n_idx = torch.tensor([v[4]], dtype=torch.int64, device="cuda")
+        return ctx.render(models[v[0]], v[1], v[2], cfg, idx=v[3], n_idx=n_idx)[0]
+    return ctx.render(models[v[0]], v[1], v[2], cfg)[0]
+
+
+@pytest.mark.parametrize("per_launch", [0, 4, 1])
+def test_batch_equals_single_views(ctx, batch_setup, per_launch):
+    scenes, models, views = batch_setup
+    cfg = _lib.default_cfg()
+    out = ctx.render_batch(models, views, cfg, views_per_launch=per_launch)
+    for k, v in enumerate(views):
+        ref = single(ctx, models, v, cfg)
+        assert torch.equal(out[k], ref), k
+
+
+def test_batch_matches_oracle(ctx, batch_setup):
+    scenes, models, views = batch_setup
+    out = ctx.render_batch(models, views[:4]).cpu().numpy()
+    st = oracle_settings()
+    for k, v in enumerate(views[:4]):
+        idx = v[3][: v[4]].cpu().numpy().view(np.uint32).astype(np.int64) if len(v) > 3 else None
+        ref = oc.render(scenes[v[0]].arrays(), v[1], v[2], st, idx=idx, mode="rect")
+        compare_image(out[k], ref)
+
+
+def test_graph_replays_match_eager(ctx, batch_setup):
+    scenes, models, views = batch_setup
+    cfg = _lib.default_cfg(instance_capacity=400_000)
+    eager = ctx.render_batch(models, views, cfg, views_per_launch=4).clone()
+    out = torch.zeros_like(eager)
+    for rep in range(4):
+        out.zero_()
+        ctx.render_batch(models, views, cfg, views_per_launch=4, use_graph=True, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        # unrelated eager work between replays
+        ctx.render(models[0], views[1][1], 0.3)
+        torch.cuda.synchronize()
+    ctx.check_overflow()
+    # a changed view rebuilds the graph
+    views2 = list(views)
+    views2[2] = (views[2][0], views[2][1], 0.77)
+    out2 = ctx.render_batch(models, views2, cfg, views_per_launch=4, use_graph=True)
+    ref2 = single(ctx, models, views2[2], _lib.default_cfg())
+    assert torch.equal(out2[2], ref2)
+    assert torch.equal(out2[0], eager[0])
+
+
+def test_autotune_configs_identical(ctx, batch_setup):
+    scenes, models, views = batch_setup
+    best, results = ctx.autotune(models, views[:5], repeats=2)
+    assert len(results) == 21
+    assert all(r["identical"] for r in results)
+    assert (best.tile_w, best.tile_h) in [(8, 8), (16, 16), (32, 8)]
+    assert best.batch in (64, 128, 256) and best.pixels_per_thread in (1, 2, 4)
+    fastest = min(results, key=lambda r: r["ms"])
+    assert fastest["ms"] > 0

@@ -187,12 +187,16 @@ def test_tile_and_batch_configs_give_identical_images(ctx):
     for tile in ((16, 16), (8, 8), (32, 8)):
         for batch in (64, 128, 256):
             for cull in (1, 0):
-                cfg = _lib.default_cfg(tile_w=tile[0], tile_h=tile[1], batch=batch, temporal_cull=cull)
-                rgb, _, _ = ctx.render(model, cam, 0.5, cfg)
-                if base is None:
-                    base = rgb.clone()
-                else:
-                    assert torch.equal(rgb, base), (tile, batch, cull)
+                for ppt in (1, 2, 4):
+                    cfg = _lib.default_cfg(tile_w=tile[0], tile_h=tile[1], batch=batch, temporal_cull=cull,
+                                           pixels_per_thread=ppt)
+                    rgb, _, _ = ctx.render(model, cam, 0.5, cfg)
+                    if base is None:
+                        base = rgb.clone()
+                    else:
+                        diff = (rgb - base).abs()
+                        assert torch.equal(rgb, base), (tile, batch, cull, ppt, int((diff > 0).sum()),
+                                                        float(diff.max()))
 
 
 def test_forward_is_deterministic(ctx):
