@@ -142,6 +142,7 @@ struct fdgs_ctx {
     std::vector<Buf> batch_tables;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;   // graphs are captured here (the caller's may be the null stream)
     std::vector<unsigned char> graph_key;
     Buf tune_ref, tune_img, tune_diff;
 
@@ -237,6 +238,7 @@ fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
     for (Buf &b : ctx->batch_tables) release(b);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     release(ctx->tune_ref);
     release(ctx->tune_img);
     release(ctx->tune_diff);
@@ -737,12 +739,14 @@ fdgs_status fdgs_render_batch(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n
     // eager run: uploads the view tables and sizes every buffer
     if (fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, cfg, per, true, out_rgb, stream)) return st;
     HIP_TRY(hipStreamSynchronize(stream));
-    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    if (!ctx->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->capture_stream;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     ctx->capturing = true;
-    fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, cfg, per, false, out_rgb, stream);
+    fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, cfg, per, false, out_rgb, cs);
     ctx->capturing = false;
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(stream, &g);
+    hipError_t e = hipStreamEndCapture(cs, &g);
     if (st != FDGS_OK) {
         if (g) (void)hipGraphDestroy(g);
         return st;

@@ -113,31 +113,51 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
                 const float4 q = make_float4(g.z, g.w, h.x, h.y);
                 const float dx = fx - g.x;
                 const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
-                bool any_left = false;
-#pragma unroll
-                for (int p = 0; p < PPT; ++p) {
-                    if (done[p]) continue;
-                    const float e = exp2_at(q, A, B, fy[p] - g.y);
+                const uint32_t pos = base + k - start + 1;
+                if constexpr (PPT == 1) {
+                    // one pixel: branch, so a wavefront skips the blend when no lane takes it
+                    const float e = exp2_at(q, A, B, fy[0] - g.y);
                     const float alpha = fminf(amax, q.w * __builtin_amdgcn_exp2f(e));
-                    if (alpha >= amin) {
-                        const float test = T[p] * (1.0f - alpha);
-                        if (test < tmin) {
-                            done[p] = true;
-                            stop[p] = base + k - start + 1;
-                            continue;
-                        }
-                        const float w = alpha * T[p];
-                        C0[p] += h.z * w;
-                        C1[p] += h.w * w;
-                        C2[p] += s_b[k] * w;
-                        T[p] = test;
-                        last[p] = base + k - start + 1;
+                    if (alpha < amin) continue;
+                    const float test = T[0] * (1.0f - alpha);
+                    if (test < tmin) {
+                        done[0] = true;
+                        stop[0] = pos;
+                        all_done = true;
+                        break;
                     }
-                    any_left = true;
-                }
-                if (!any_left) {
-                    all_done = true;
-                    break;
+                    const float w = alpha * T[0];
+                    C0[0] = fmaf(h.z, w, C0[0]);
+                    C1[0] = fmaf(h.w, w, C1[0]);
+                    C2[0] = fmaf(s_b[k], w, C2[0]);
+                    T[0] = test;
+                    last[0] = pos;
+                } else {
+                    // several pixels: predicated updates, no divergent branches per pixel
+                    const float cb = s_b[k];
+                    bool left = false;
+#pragma unroll
+                    for (int p = 0; p < PPT; ++p) {
+                        const float e = exp2_at(q, A, B, fy[p] - g.y);
+                        const float alpha = fminf(amax, q.w * __builtin_amdgcn_exp2f(e));
+                        const float test = T[p] * (1.0f - alpha);
+                        const bool take = !done[p] && alpha >= amin;
+                        const bool stp = take && test < tmin;
+                        const bool use = take && !stp;
+                        const float w = use ? alpha * T[p] : 0.0f;
+                        C0[p] = fmaf(h.z, w, C0[p]);
+                        C1[p] = fmaf(h.w, w, C1[p]);
+                        C2[p] = fmaf(cb, w, C2[p]);
+                        T[p] = use ? test : T[p];
+                        last[p] = use ? pos : last[p];
+                        stop[p] = stp ? pos : stop[p];
+                        done[p] = done[p] || stp;
+                        left = left || !done[p];
+                    }
+                    if (!left) {
+                        all_done = true;
+                        break;
+                    }
                 }
             }
         }

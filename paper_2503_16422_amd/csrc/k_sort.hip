@@ -22,15 +22,16 @@ namespace fdgs {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kRounds = 16;
-constexpr int kChunk = kNT * kRounds;   // keys per block
+constexpr int kNW = kNT / 64;
 constexpr int kRadix = 256;
 
 __device__ __forceinline__ int64_t count_of(const int64_t *n_dev, int64_t n_max) {
     return n_dev ? min(*n_dev, n_max) : n_max;
 }
 
-// Per-block digit histogram, stored digit-major: hist[d * nb + b].
+// Per-block digit histogram, stored digit-major: hist[d * nb + b].  Block b
+// owns keys [b * KPT * kNT, (b + 1) * KPT * kNT).
+template <int KPT>
 __global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, const int64_t *n_dev,
                                                       int64_t n_max, int shift, uint32_t mask,
                                                       uint32_t *hist) {
@@ -38,8 +39,9 @@ __global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, cons
     const int64_t n = count_of(n_dev, n_max);
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    for (int r = 0; r < kRounds; ++r) {
+    const int64_t base = (int64_t)blockIdx.x * (KPT * kNT);
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
         const int64_t j = base + (int64_t)r * kNT + threadIdx.x;
         if (j < n) atomicAdd(&h[(keys[j] >> shift) & mask], 1u);
     }
@@ -65,70 +67,75 @@ __global__ void __launch_bounds__(1024) rowscan_kernel(uint32_t *hist, int64_t n
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter.  Round r: thread t takes key base + r*kNT + t.  Lanes with
-// equal digits are found with one ballot per digit bit; a lane's rank is the
-// number of matching lanes below it; per-wave digit counts in shared memory
-// give the offsets of earlier waves; a running per-digit base carries across
-// rounds.  Thread t also owns digit t for the bookkeeping.
+// Stable scatter of one block's KPT * kNT keys.  Wave w owns the contiguous
+// slice [w * KPT * 64, (w + 1) * KPT * 64) of the block's keys and ranks it
+// alone: per round of 64 keys, lanes with equal digits are found with one
+// ballot per digit bit, and a per-wave running count per digit in LDS gives
+// each key its rank among the wave's keys with that digit.  One block barrier
+// then turns the per-wave counts into offsets (earlier waves first), and every
+// key is written to global base + wave offset + rank.  Keys keep their order
+// within a digit, so the sort is stable.
+template <int KPT>
 __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, const uint32_t *vals,
                                                         uint32_t *keys_out, uint32_t *vals_out,
                                                         const int64_t *n_dev, int64_t n_max,
                                                         int shift, int bits, const uint32_t *hist,
                                                         const uint32_t *digit_total) {
-    constexpr int NW = kNT / 64;
-    __shared__ uint32_t s_base[kRadix];      // next output slot of each digit for this block
-    __shared__ uint32_t s_cnt[NW][kRadix];   // per-wave digit counts -> offsets
-    __shared__ uint32_t s_tmp[kNT / 64 + 1];
+    __shared__ uint32_t s_cnt[kNW][kRadix];   // per-wave digit counts, then per-wave output offsets
+    __shared__ uint32_t s_tmp[kNW + 1];
     const int64_t n = count_of(n_dev, n_max);
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    const uint32_t mask = (1u << bits) - 1u;
-    const int dd = threadIdx.x;
-    {
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_sum<kNT>(digit_total[dd], s_tmp, &tot);
-        s_base[dd] = ex + hist[(int64_t)dd * gridDim.x + blockIdx.x];
-    }
     const int lane = lane_id(), w = wave_id();
+    const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int r = 0; r < kRounds; ++r) {
-        const int64_t rb = base + (int64_t)r * kNT;
-        if (rb >= n) break;                  // uniform across the block
 #pragma unroll
-        for (int k = 0; k < NW; ++k) s_cnt[k][dd] = 0;
-        __syncthreads();
-        const int64_t j = rb + threadIdx.x;
+    for (int k = 0; k < kRadix / 64; ++k) s_cnt[w][k * 64 + lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int64_t wbase = (int64_t)blockIdx.x * (KPT * kNT) + (int64_t)w * (KPT * 64);
+    uint32_t key[KPT], val[KPT], rank[KPT];
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int64_t j = wbase + (int64_t)r * 64 + lane;
         const bool valid = j < n;
-        uint32_t key = 0, val = 0, d = 0;
-        if (valid) {
-            key = keys[j];
-            val = vals[j];
-            d = (key >> shift) & mask;
-        }
+        key[r] = valid ? keys[j] : 0u;
+        val[r] = valid ? vals[j] : 0u;
+        const uint32_t d = (key[r] >> shift) & mask;
         uint64_t match = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t bb = __ballot(bit);
             match &= bit ? bb : ~bb;
         }
-        const uint32_t rank = __popcll(match & lt_mask);
+        const uint32_t before = __popcll(match & lt_mask);
         const uint32_t cnt = __popcll(match);
-        if (valid && rank == cnt - 1) s_cnt[w][d] = cnt;   // last lane of its group
-        __syncthreads();
-        uint32_t round_tot = 0;
+        const uint32_t run = valid ? s_cnt[w][d] : 0u;
+        rank[r] = run + before;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == cnt - 1) s_cnt[w][d] = run + cnt;   // last lane of its group
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int dd = threadIdx.x;                  // thread dd owns digit dd
+    uint32_t tot;
+    const uint32_t gbase = block_exclusive_sum<kNT>(digit_total[dd], s_tmp, &tot) +
+                           hist[(int64_t)dd * gridDim.x + blockIdx.x];
+    uint32_t run = gbase;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const uint32_t c = s_cnt[k][dd];
-            s_cnt[k][dd] = round_tot;
-            round_tot += c;
+    for (int k = 0; k < kNW; ++k) {
+        const uint32_t c = s_cnt[k][dd];
+        s_cnt[k][dd] = run;
+        run += c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int64_t j = wbase + (int64_t)r * 64 + lane;
+        if (j < n) {
+            const uint32_t pos = s_cnt[w][(key[r] >> shift) & mask] + rank[r];
+            keys_out[pos] = key[r];
+            vals_out[pos] = val[r];
         }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = s_base[d] + s_cnt[w][d] + rank;
-            keys_out[pos] = key;
-            vals_out[pos] = val;
-        }
-        __syncthreads();
-        s_base[dd] += round_tot;
     }
 }
 
@@ -252,15 +259,25 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
     if (j < n) p[j] = v;
 }
 
-__global__ void ranges_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max,
+// Tile ranges by binary search: tile t's list is [lower_bound(t), lower_bound(t + 1))
+// in the sorted keys, so every tile (empty ones too) is written by one thread.
+__global__ void ranges_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max, int32_t n_tiles,
                               uint32_t *ranges) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
     const int64_t n = count_of(n_dev, n_max);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const uint32_t t = keys[j];
-    if (j == 0 || keys[j - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)j;
-    if (j == n - 1 || keys[j + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(j + 1);
+    auto lower = [&](uint32_t key) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    ranges[2 * t] = (uint32_t)lower((uint32_t)t);
+    ranges[2 * t + 1] = (uint32_t)lower((uint32_t)t + 1u);
 }
+
 
 __global__ void accumulate_counts_kernel(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
                                          int64_t capacity, unsigned long long *acc) {
@@ -275,16 +292,34 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) /
 
 }  // namespace
 
+// Keys per thread: small sorts use short chunks so that more blocks run.
+inline int sort_kpt(int64_t n_max) { return n_max <= (int64_t(1) << 20) ? 4 : 16; }
+
 size_t sort_scratch_bytes(int64_t n_max) {
-    const int64_t nb = (n_max + kChunk - 1) / kChunk;
+    const int64_t chunk = (int64_t)sort_kpt(n_max) * kNT;
+    const int64_t nb = (n_max + chunk - 1) / chunk;
     return sizeof(uint32_t) * (size_t)(kRadix * (nb > 0 ? nb : 1) + kRadix);
+}
+
+template <int KPT>
+static void sort_pass(const uint32_t *src_k, const uint32_t *src_v, uint32_t *dst_k, uint32_t *dst_v,
+                      const int64_t *n_dev, int64_t n_max, int shift, int bits, uint32_t *hist,
+                      uint32_t *digit_total, int64_t nb, hipStream_t s) {
+    const uint32_t mask = (1u << bits) - 1u;
+    hipLaunchKernelGGL((upsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, n_dev, n_max, shift,
+                       mask, hist);
+    hipLaunchKernelGGL(rowscan_kernel, dim3(kRadix), dim3(1024), 0, s, hist, nb, digit_total);
+    hipLaunchKernelGGL((downsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, src_v, dst_k, dst_v,
+                       n_dev, n_max, shift, bits, (const uint32_t *)hist, (const uint32_t *)digit_total);
 }
 
 hipError_t radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                           const int64_t *n_dev, int64_t n_max, int begin_bit, int end_bit,
                           void *scratch, int *result_in_alt, hipStream_t s) {
     *result_in_alt = 0;
-    const int64_t nb = (n_max + kChunk - 1) / kChunk;
+    const int kpt = sort_kpt(n_max);
+    const int64_t chunk = (int64_t)kpt * kNT;
+    const int64_t nb = (n_max + chunk - 1) / chunk;
     if (nb == 0 || end_bit <= begin_bit) return hipSuccess;
     uint32_t *hist = static_cast<uint32_t *>(scratch);
     uint32_t *digit_total = hist + (size_t)kRadix * nb;
@@ -292,13 +327,10 @@ hipError_t radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, ui
     int alt = 0;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         const int bits = min(8, end_bit - shift);
-        const uint32_t mask = (1u << bits) - 1u;
-        hipLaunchKernelGGL(upsweep_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, src_k, n_dev, n_max,
-                           shift, mask, hist);
-        hipLaunchKernelGGL(rowscan_kernel, dim3(kRadix), dim3(1024), 0, s, hist, nb, digit_total);
-        hipLaunchKernelGGL(downsweep_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, src_k, src_v,
-                           dst_k, dst_v, n_dev, n_max, shift, bits, (const uint32_t *)hist,
-                           (const uint32_t *)digit_total);
+        if (kpt == 4)
+            sort_pass<4>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, s);
+        else
+            sort_pass<16>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, s);
         uint32_t *tk = src_k, *tv = src_v;
         src_k = dst_k; src_v = dst_v; dst_k = tk; dst_v = tv;
         alt ^= 1;
@@ -363,11 +395,9 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 
 hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
                               int32_t n_tiles, uint32_t *ranges, hipStream_t s) {
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(2 * (int64_t)n_tiles, 256)), dim3(256), 0, s,
-                       ranges, 2 * (int64_t)n_tiles, 0u);
-    if (n_max > 0)
-        hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, tile_keys,
-                           n_inst_dev, n_max, ranges);
+    if (n_tiles > 0)
+        hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n_tiles, 256)), dim3(256), 0, s, tile_keys, n_inst_dev,
+                           n_max, n_tiles, ranges);
     return hipGetLastError();
 }
 

@@ -99,3 +99,40 @@ def test_autograd_function_matches_direct_call(ctx):
     ctx.release(state)
     for p, k in zip(params, NAMES):
         assert torch.allclose(p.grad, direct[k], rtol=1e-5, atol=1e-6 * float(direct[k].abs().max()) + 1e-12), k
+
+
+def crop_camera(cam, x0, y0, w, h):
+    """The same pinhole restricted to pixels [x0, x0 + w) x [y0, y0 + h)."""
+    c = inputs.Camera(cam.R, cam.tvec, cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, w, h, cam.znear)
+    return c
+
+
+@pytest.mark.parametrize("crop", [(600, 480), (1320, 990)])
+def test_backward_full_scene_on_crops(ctx, crop):
+    """500k-Gaussian scene, 1352x1014 camera: the gradient of a 32x32 crop.
+    Gaussians whose footprint misses the crop contribute nothing, so the
+    oracle differentiates only the ones that reach it."""
+    from oracle import composite as oc
+    from paper_2503_16422_amd.render import GaussianModel
+    sc = inputs.dense_scene(500_000, seed=0)
+    cam = crop_camera(inputs.arc_cameras(20, 4.0, 1352, 1014)[5], crop[0], crop[1], 32, 32)
+    t = 0.6001
+    model = GaussianModel.from_scene(sc, "cuda:0")
+    rgb, _, state = ctx.render(model, cam, t, keep_state=True)
+    G = np.random.default_rng(3).standard_normal((3, 32, 32))
+    grads = ctx.backward(state, torch.from_numpy(G.astype(np.float32)).cuda(), model)
+    torch.cuda.synchronize()
+    ctx.release(state)
+    st = oracle_settings()
+    pre = oc.prepare(sc.arrays(), cam, t, st)
+    keep = np.flatnonzero(pre.visible)
+    assert 0 < keep.size < 20_000
+    ref = og.render_vjp(sc.subset(keep).arrays(), cam, t, st, G)
+    sub = {k: grads[k][..., torch.from_numpy(keep).cuda()] for k in NAMES}
+    errs = check_grads(sub, ref)
+    drop = np.ones(sc.n, dtype=bool)
+    drop[keep] = False
+    dropped = torch.from_numpy(drop).cuda()
+    for k in NAMES:
+        assert torch.all(grads[k][..., dropped] == 0), k
+    print(f"crop {crop}: {keep.size} Gaussians reach it; errors " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
