@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the masked headline loop (for profiler runs)")
+    ap.add_argument("--config", default=None,
+                    help="tile_w,tile_h,batch,pixels_per_thread: skip the autotuner and use this configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -317,8 +319,13 @@ def main():
         c, f = frame_schedule(k * 13, len(cams), len(frames))
         idx, cnt = masks[frame_window[f]]
         tune_views.append((0, cams[c], float(frames[f]), idx, int(cnt.item())))
-    best, sweep = ctx.autotune([model], tune_views, _lib.default_cfg(), views_per_launch=1, repeats=2)
-    tuned = dict(tile_w=best.tile_w, tile_h=best.tile_h, batch=best.batch, pixels_per_thread=best.pixels_per_thread)
+    if args.config:
+        tw, th, b, p = (int(x) for x in args.config.split(","))
+        tuned, sweep = dict(tile_w=tw, tile_h=th, batch=b, pixels_per_thread=p), []
+    else:
+        best, sweep = ctx.autotune([model], tune_views, _lib.default_cfg(), views_per_launch=1, repeats=2)
+        tuned = dict(tile_w=best.tile_w, tile_h=best.tile_h, batch=best.batch,
+                     pixels_per_thread=best.pixels_per_thread)
     log(f"[bench] autotuned {tuned}")
     worst = max_instances(ctx, model, cams, frames, masks, frame_window, _lib.default_cfg(**tuned), K + Wu, 0)
     log(f"[bench] max instances over the timed frames {worst}")

@@ -452,7 +452,6 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     HIP_TRY(ensure(S->rect, sizeof(int32_t) * 4 * n_max));
     HIP_TRY(ensure(S->tiles, sizeof(uint32_t) * n_max));
     HIP_TRY(ensure(S->visible, n_max));
-    HIP_TRY(ensure(S->vis_pos, sizeof(uint32_t) * n_max));
     HIP_TRY(ensure(S->order_k, sizeof(uint32_t) * n_max));
     HIP_TRY(ensure(S->order_v, sizeof(uint32_t) * n_max));
     HIP_TRY(ensure(S->order_k2, sizeof(uint32_t) * n_max));
@@ -478,11 +477,8 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     }
     {
         StageTimer tm(ctx, FDGS_STAGE_COMPACT, stream);
-        HIP_TRY(scan_flags_u8(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(), n_dev, n_max, counts + 0,
-                              S->scratch.p, stream));
-        HIP_TRY(launch_scatter_visible(S->visible.as<uint8_t>(), S->vis_pos.as<uint32_t>(),
-                                       S->depth_key.as<uint64_t>(), n_dev, n_max, S->order_k.as<uint32_t>(),
-                                       S->order_v.as<uint32_t>(), stream));
+        HIP_TRY(compact_visible(S->visible.as<uint8_t>(), S->depth_key.as<uint64_t>(), n_dev, n_max, counts + 0,
+                                S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->scratch.p, stream));
     }
     uint32_t *ov = nullptr;
     {
@@ -553,7 +549,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     {
         StageTimer tm(ctx, FDGS_STAGE_COMPOSITE, stream);
         HIP_TRY(launch_composite(rp, W, H, V, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
-                                 out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
+                                 S->rect.as<int32_t>(), out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
                                  acc ? acc + 3 : nullptr,
                                  cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt, stream));
     }

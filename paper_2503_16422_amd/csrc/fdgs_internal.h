@@ -86,6 +86,9 @@ hipError_t scan_flags_u8(const uint8_t *in, uint32_t *out, const int64_t *n_dev,
 hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t *out,
                            const int64_t *n_dev, int64_t n_max, int64_t *total,
                            void *scratch, hipStream_t s);
+// Visible entries in order -> keys32 = float32 bits of their depth, vals = position; *total = count.
+hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
+                           int64_t *total, uint32_t *keys32, uint32_t *vals, void *scratch, hipStream_t s);
 hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t *count,
                         void *scratch, hipStream_t s);
 size_t compact_scratch_bytes(int64_t n);
@@ -126,7 +129,7 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 // V views of W x H share one tile grid: block b renders tile b % n_tiles of
 // view b / n_tiles; view v writes out_rgb + v*3*W*H (out_T, n_contrib: + v*W*H).
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
-                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
                             uint64_t *pair_counter, int32_t pixels_per_thread, hipStream_t s);
 

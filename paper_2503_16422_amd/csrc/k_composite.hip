@@ -55,11 +55,28 @@ struct CompArgs {
     unsigned long long *pairs;   // optional counter of evaluated pairs
     int32_t ppt;                 // pixels per thread (host-side dispatch only)
     int32_t V;                   // views sharing the launch
+    const int4 *rect;            // inclusive pixel rect of each processed Gaussian
 };
 
-// Thread layout: PPT consecutive pixels of one column per thread
-// (TW x TH / PPT threads); the column's dx terms and the LDS reads of a record
-// are shared by the thread's PPT pixels.
+// Thread layout.  PPT == 1: each wavefront owns an 8x8 block of the tile.
+// PPT > 1: PPT consecutive pixels of one column per thread (TW x TH / PPT
+// threads); the column's dx terms and the LDS reads of a record are shared by
+// the thread's PPT pixels.  Either way a wavefront skips, with one uniform
+// branch, every staged Gaussian whose pixel rectangle misses the pixels it
+// owns (those pixels would all fail the alpha test).
+template <int TW, int TH, int PPT>
+__device__ __forceinline__ void pixel_of_thread(int t, int &lx, int &ly0) {
+    if constexpr (PPT == 1) {
+        const int w = t >> 6, l = t & 63;
+        constexpr int QX = TW / 8;                    // 8x8 blocks per tile row
+        lx = (w % QX) * 8 + (l & 7);
+        ly0 = (w / QX) * 8 + (l >> 3);
+    } else {
+        lx = t % TW;
+        ly0 = (t / TW) * PPT;
+    }
+}
+
 template <int TW, int TH, int BATCH, int PPT>
 __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
     constexpr int NT = TW * TH / PPT;
@@ -67,12 +84,26 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
     __shared__ float4 s_g[BATCH];    // centre (block-relative), ka, kb
     __shared__ float4 s_h[BATCH];    // kc, opacity, r, g
     __shared__ float s_b[BATCH];     // b
+    __shared__ int4 s_r[BATCH];      // pixel rect
     const int n_tiles = a.rp.tiles_x * a.rp.tiles_y;
     const int view = blockIdx.x / n_tiles;
     const int tile = blockIdx.x - view * n_tiles;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
-    const int lx = threadIdx.x % TW, ly0 = (threadIdx.x / TW) * PPT;
+    int lx, ly0;
+    pixel_of_thread<TW, TH, PPT>(threadIdx.x, lx, ly0);
     const int px = tx * TW + lx, py0 = ty * TH + ly0;
+    // pixel box of this wavefront (the first and last lane bound it)
+    int wx0, wy0, wx1, wy1;
+    {
+        int l0x, l0y, l1x, l1y;
+        const int wfirst = threadIdx.x & ~63;
+        pixel_of_thread<TW, TH, PPT>(wfirst, l0x, l0y);
+        pixel_of_thread<TW, TH, PPT>(wfirst + 63, l1x, l1y);
+        wx0 = tx * TW + (PPT == 1 ? l0x : 0);
+        wx1 = tx * TW + (PPT == 1 ? l1x : TW - 1);
+        wy0 = ty * TH + l0y;
+        wy1 = ty * TH + l1y + PPT - 1;
+    }
     // Offsets are taken from the origin of the enclosing 32x32 block, which is
     // the same for every tile shape, so a pixel's arithmetic does not depend on
     // the tiling.
@@ -99,15 +130,20 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
         if (__syncthreads_count(!all_done) == 0) break;
         const int cnt = (int)min((uint32_t)BATCH, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) {
-            const Rec2D r = a.rec[a.ids[base + k]];
+            const uint32_t id = a.ids[base + k];
+            const Rec2D r = a.rec[id];
             const float4 q = staged_conic(r);
             s_g[k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
             s_h[k] = make_float4(q.z, q.w, r.c.x, r.c.y);
             s_b[k] = r.c.z;
+            s_r[k] = a.rect[id];
         }
         __syncthreads();
         if (!all_done) {
             for (int k = 0; k < cnt; ++k) {
+                const int4 rr = s_r[k];
+                const bool miss = rr.z < wx0 || rr.x > wx1 || rr.w < wy0 || rr.y > wy1;
+                if (__builtin_amdgcn_readfirstlane((int)miss)) continue;
                 const float4 g = s_g[k];
                 const float4 h = s_h[k];
                 const float4 q = make_float4(g.z, g.w, h.x, h.y);
@@ -322,6 +358,7 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
 
 template <int TW, int TH, int BATCH, int PPT>
 void launch_fwd_ppt(const CompArgs &a, int n_tiles, hipStream_t s) {
+    static_assert(PPT > 1 || (TW % 8 == 0 && TH % 8 == 0), "8x8 blocks per wavefront");
     hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
 }
 
@@ -371,12 +408,12 @@ void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
     } while (0)
 
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
-                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
                             uint64_t *pair_counter, int32_t ppt, hipStream_t s) {
     if (ppt != 1 && ppt != 2 && ppt != 4) return hipErrorInvalidValue;
     CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, n_contrib,
-               reinterpret_cast<unsigned long long *>(pair_counter), ppt, V};
+               reinterpret_cast<unsigned long long *>(pair_counter), ppt, V, reinterpret_cast<const int4 *>(rect)};
     const int n_tiles = rp.tiles_x * rp.tiles_y * V;
     FDGS_DISPATCH(launch_fwd, a);
     return hipGetLastError();

@@ -101,6 +101,35 @@ hipError_t scan_impl(Load ld, Out *out, const int64_t *n_dev, int64_t n_max, int
     return hipGetLastError();
 }
 
+// Visible compaction: the downsweep of a scan over the visible flags that
+// writes each visible entry's (float32 depth bits, position) to its slot.
+__global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *visible, const uint64_t *depth_key,
+                                                              const int64_t *n_dev, int64_t n_max,
+                                                              const uint64_t *partial, uint32_t *keys32,
+                                                              uint32_t *vals) {
+    __shared__ uint64_t tmp[kNT / 64 + 1];
+    const int64_t n = count_of(n_dev, n_max);
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        v[k] = base + k < n ? visible[base + k] : 0u;
+        s += v[k];
+    }
+    uint64_t total;
+    uint64_t run = block_exclusive_sum<kNT>(s, tmp, &total) + partial[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (v[k]) {
+            const double z = __longlong_as_double((long long)depth_key[base + k]);
+            keys32[run] = __float_as_uint((float)z);   // z > 0: bit order = value order
+            vals[run] = (uint32_t)(base + k);
+            ++run;
+        }
+    }
+}
+
 // --- compaction of active-set bits -----------------------------------------
 // Each block covers kChunk Gaussians (kChunk/32 bit words).
 __global__ void __launch_bounds__(kNT) bits_count_kernel(const uint32_t *bits, int64_t nw,
@@ -162,6 +191,20 @@ hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t 
                            const int64_t *n_dev, int64_t n_max, int64_t *total, void *scratch,
                            hipStream_t s) {
     return scan_impl(LoadU32{in, gather}, out, n_dev, n_max, total, scratch, s);
+}
+
+hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
+                           int64_t *total, uint32_t *keys32, uint32_t *vals, void *scratch, hipStream_t s) {
+    const int64_t nb = (n_max + kChunk - 1) / kChunk;
+    uint64_t *partial = static_cast<uint64_t *>(scratch);
+    if (nb > 0)
+        hipLaunchKernelGGL((reduce_kernel<LoadU8>), dim3((unsigned)nb), dim3(kNT), 0, s, LoadU8{visible}, n_dev, n_max,
+                           partial);
+    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total);
+    if (nb > 0)
+        hipLaunchKernelGGL(compact_visible_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, visible, depth_key, n_dev,
+                           n_max, (const uint64_t *)partial, keys32, vals);
+    return hipGetLastError();
 }
 
 hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t *count,

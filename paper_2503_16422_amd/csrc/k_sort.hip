@@ -72,16 +72,20 @@ __global__ void __launch_bounds__(1024) rowscan_kernel(uint32_t *hist, int64_t n
 // alone: per round of 64 keys, lanes with equal digits are found with one
 // ballot per digit bit, and a per-wave running count per digit in LDS gives
 // each key its rank among the wave's keys with that digit.  One block barrier
-// then turns the per-wave counts into offsets (earlier waves first), and every
-// key is written to global base + wave offset + rank.  Keys keep their order
-// within a digit, so the sort is stable.
+// turns the per-wave counts into block-local digit offsets (earlier waves
+// first); the keys are reordered by digit in LDS and then written out by
+// consecutive threads, so each digit's run leaves the block as contiguous,
+// coalesced stores.  Keys keep their order within a digit: the sort is stable.
 template <int KPT>
 __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, const uint32_t *vals,
                                                         uint32_t *keys_out, uint32_t *vals_out,
                                                         const int64_t *n_dev, int64_t n_max,
                                                         int shift, int bits, const uint32_t *hist,
                                                         const uint32_t *digit_total) {
-    __shared__ uint32_t s_cnt[kNW][kRadix];   // per-wave digit counts, then per-wave output offsets
+    constexpr int CH = KPT * kNT;
+    __shared__ uint32_t s_cnt[kNW][kRadix];   // per-wave digit counts, then block-local offsets
+    __shared__ uint32_t s_gap[kRadix];        // global start minus block-local start, per digit
+    __shared__ uint32_t s_key[CH], s_val[CH];
     __shared__ uint32_t s_tmp[kNW + 1];
     const int64_t n = count_of(n_dev, n_max);
     const int lane = lane_id(), w = wave_id();
@@ -91,7 +95,8 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
     for (int k = 0; k < kRadix / 64; ++k) s_cnt[w][k * 64 + lane] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const int64_t wbase = (int64_t)blockIdx.x * (KPT * kNT) + (int64_t)w * (KPT * 64);
+    const int64_t bbase = (int64_t)blockIdx.x * CH;
+    const int64_t wbase = bbase + (int64_t)w * (KPT * 64);
     uint32_t key[KPT], val[KPT], rank[KPT];
 #pragma unroll
     for (int r = 0; r < KPT; ++r) {
@@ -120,7 +125,12 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
     uint32_t tot;
     const uint32_t gbase = block_exclusive_sum<kNT>(digit_total[dd], s_tmp, &tot) +
                            hist[(int64_t)dd * gridDim.x + blockIdx.x];
-    uint32_t run = gbase;
+    uint32_t dcount = 0;
+#pragma unroll
+    for (int k = 0; k < kNW; ++k) dcount += s_cnt[k][dd];
+    const uint32_t lbase = block_exclusive_sum<kNT>(dcount, s_tmp, &tot);
+    s_gap[dd] = gbase - lbase;
+    uint32_t run = lbase;
 #pragma unroll
     for (int k = 0; k < kNW; ++k) {
         const uint32_t c = s_cnt[k][dd];
@@ -132,9 +142,21 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
     for (int r = 0; r < KPT; ++r) {
         const int64_t j = wbase + (int64_t)r * 64 + lane;
         if (j < n) {
-            const uint32_t pos = s_cnt[w][(key[r] >> shift) & mask] + rank[r];
-            keys_out[pos] = key[r];
-            vals_out[pos] = val[r];
+            const uint32_t lpos = s_cnt[w][(key[r] >> shift) & mask] + rank[r];
+            s_key[lpos] = key[r];
+            s_val[lpos] = val[r];
+        }
+    }
+    __syncthreads();
+    const int valid_n = (int)min((int64_t)CH, n - bbase);
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int i = r * kNT + threadIdx.x;
+        if (i < valid_n) {
+            const uint32_t k = s_key[i];
+            const uint32_t pos = s_gap[(k >> shift) & mask] + (uint32_t)i;
+            keys_out[pos] = k;
+            vals_out[pos] = s_val[i];
         }
     }
 }
@@ -193,6 +215,7 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
 // position inside the Gaussian's tile rectangle (row-major), so a Gaussian
 // covering thousands of tiles is spread over the whole block.
 constexpr int kDupNT = 256;
+constexpr int kDupRun = 8;
 
 __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order, const uint64_t *offsets,
                                                            const int32_t *rect, const uint32_t *view_of,
@@ -224,20 +247,34 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
     }
     if (t == 0) s_off[cnt] = (j0 + cnt < n_vis) ? offsets[j0 + cnt] : (uint64_t)n_inst;
     __syncthreads();
-    const uint64_t first = s_off[0], last = s_off[cnt];
-    const uint64_t cap = (uint64_t)capacity;
-    for (uint64_t e = first + t; e < last && e < cap; e += kDupNT) {
-        int lo = 0, hi = cnt - 1;                      // largest i with s_off[i] <= e
+    const uint64_t first = s_off[0];
+    const uint64_t last = min(s_off[cnt], (uint64_t)capacity);
+    // each thread writes kDupRun consecutive instances: one search per run
+    for (uint64_t e0 = first + (uint64_t)t * kDupRun; e0 < last; e0 += (uint64_t)kDupNT * kDupRun) {
+        int lo = 0, hi = cnt - 1;                      // largest i with s_off[i] <= e0
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+            if (s_off[mid] <= e0) lo = mid; else hi = mid - 1;
         }
-        const uint32_t k = (uint32_t)(e - s_off[lo]);
-        const int w = s_w[lo];
-        const int ty = s_ty0[lo] + (int)(k / (uint32_t)w);
-        const int tx = s_tx0[lo] + (int)(k % (uint32_t)w);
-        tile_keys[e] = s_base[lo] + (uint32_t)(ty * rp.tiles_x + tx);
-        ids[e] = s_id[lo];
+        int w = s_w[lo];
+        const uint32_t k = (uint32_t)(e0 - s_off[lo]);
+        int ry = (int)(k / (uint32_t)w);
+        int rx = (int)k - ry * w;
+        const uint64_t e1 = min(e0 + kDupRun, last);
+        for (uint64_t e = e0; e < e1; ++e) {
+            if (e == s_off[lo + 1]) {                  // next Gaussian starts here
+                ++lo;
+                w = s_w[lo];
+                rx = 0;
+                ry = 0;
+            }
+            tile_keys[e] = s_base[lo] + (uint32_t)((s_ty0[lo] + ry) * rp.tiles_x + s_tx0[lo] + rx);
+            ids[e] = s_id[lo];
+            if (++rx == w) {
+                rx = 0;
+                ++ry;
+            }
+        }
     }
 }
 
