@@ -23,18 +23,19 @@ namespace {
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.69314718055994531f;
 
-// Staged form of a record's conic: base-2 exponent coefficients, so that
-// G = exp(-1/2 d^T conic d) = exp2(ka dx^2 + kb dx dy + kc dy^2).
+// Staged form of a record's conic and opacity: base-2 exponent coefficients
+// and log2(opacity), so that
+//   opacity * exp(-1/2 d^T conic d) = exp2(ka dx^2 + kb dx dy + kc dy^2 + lo).
 __device__ __forceinline__ float4 staged_conic(const Rec2D &r) {
-    return make_float4(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y, -0.5f * kLog2e * r.b.z, r.b.w);
+    return make_float4(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y, -0.5f * kLog2e * r.b.z, __log2f(r.b.w));
 }
 
-// Base-2 exponent of the 2D Gaussian at offset (dx, dy):
-//   e = (ka dx) dx + dy (kb dx + kc dy).
+// Base-2 exponent of opacity x 2D Gaussian at offset (dx, dy):
+//   e = ((ka dx) dx + lo) + dy (kb dx + kc dy).
 // The dx-only terms are computed once per column when a thread owns several
 // pixels of one column; every kernel evaluates exactly this expression, so
 // forward, adjoint and all tile shapes take identical alpha decisions.
-__device__ __forceinline__ float exp2_col_a(float4 q, float dx) { return (q.x * dx) * dx; }
+__device__ __forceinline__ float exp2_col_a(float4 q, float dx) { return fmaf(q.x * dx, dx, q.w); }
 __device__ __forceinline__ float exp2_col_b(float4 q, float dx) { return q.y * dx; }
 __device__ __forceinline__ float exp2_at(float4 q, float A, float B, float dy) {
     return fmaf(dy, fmaf(q.z, dy, B), A);
@@ -42,6 +43,8 @@ __device__ __forceinline__ float exp2_at(float4 q, float A, float B, float dy) {
 __device__ __forceinline__ float gauss_exp2(float4 q, float dx, float dy) {
     return exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), dy);
 }
+// Transmittance after blending alpha in front of T.
+__device__ __forceinline__ float after(float T, float alpha) { return fmaf(-alpha, T, T); }
 
 struct CompArgs {
     RenderParams rp;
@@ -55,55 +58,24 @@ struct CompArgs {
     unsigned long long *pairs;   // optional counter of evaluated pairs
     int32_t ppt;                 // pixels per thread (host-side dispatch only)
     int32_t V;                   // views sharing the launch
-    const int4 *rect;            // inclusive pixel rect of each processed Gaussian
 };
 
-// Thread layout.  PPT == 1: each wavefront owns an 8x8 block of the tile.
-// PPT > 1: PPT consecutive pixels of one column per thread (TW x TH / PPT
-// threads); the column's dx terms and the LDS reads of a record are shared by
-// the thread's PPT pixels.  Either way a wavefront skips, with one uniform
-// branch, every staged Gaussian whose pixel rectangle misses the pixels it
-// owns (those pixels would all fail the alpha test).
-template <int TW, int TH, int PPT>
-__device__ __forceinline__ void pixel_of_thread(int t, int &lx, int &ly0) {
-    if constexpr (PPT == 1) {
-        const int w = t >> 6, l = t & 63;
-        constexpr int QX = TW / 8;                    // 8x8 blocks per tile row
-        lx = (w % QX) * 8 + (l & 7);
-        ly0 = (w / QX) * 8 + (l >> 3);
-    } else {
-        lx = t % TW;
-        ly0 = (t / TW) * PPT;
-    }
-}
-
-template <int TW, int TH, int BATCH, int PPT>
+// Thread layout: PPT consecutive pixels of one column per thread
+// (TW x TH / PPT threads); the column's dx terms and the LDS reads of a record
+// are shared by the thread's PPT pixels.
+template <int TW, int TH, int BATCH, int PPT, bool COUNT>
 __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
     constexpr int NT = TW * TH / PPT;
     static_assert(NT % 64 == 0, "whole wavefronts per tile");
     __shared__ float4 s_g[BATCH];    // centre (block-relative), ka, kb
     __shared__ float4 s_h[BATCH];    // kc, opacity, r, g
     __shared__ float s_b[BATCH];     // b
-    __shared__ int4 s_r[BATCH];      // pixel rect
     const int n_tiles = a.rp.tiles_x * a.rp.tiles_y;
     const int view = blockIdx.x / n_tiles;
     const int tile = blockIdx.x - view * n_tiles;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
-    int lx, ly0;
-    pixel_of_thread<TW, TH, PPT>(threadIdx.x, lx, ly0);
+    const int lx = threadIdx.x % TW, ly0 = (threadIdx.x / TW) * PPT;
     const int px = tx * TW + lx, py0 = ty * TH + ly0;
-    // pixel box of this wavefront (the first and last lane bound it)
-    int wx0, wy0, wx1, wy1;
-    {
-        int l0x, l0y, l1x, l1y;
-        const int wfirst = threadIdx.x & ~63;
-        pixel_of_thread<TW, TH, PPT>(wfirst, l0x, l0y);
-        pixel_of_thread<TW, TH, PPT>(wfirst + 63, l1x, l1y);
-        wx0 = tx * TW + (PPT == 1 ? l0x : 0);
-        wx1 = tx * TW + (PPT == 1 ? l1x : TW - 1);
-        wy0 = ty * TH + l0y;
-        wy1 = ty * TH + l1y + PPT - 1;
-    }
     // Offsets are taken from the origin of the enclosing 32x32 block, which is
     // the same for every tile shape, so a pixel's arithmetic does not depend on
     // the tiling.
@@ -130,20 +102,15 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
         if (__syncthreads_count(!all_done) == 0) break;
         const int cnt = (int)min((uint32_t)BATCH, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) {
-            const uint32_t id = a.ids[base + k];
-            const Rec2D r = a.rec[id];
+            const Rec2D r = a.rec[a.ids[base + k]];
             const float4 q = staged_conic(r);
             s_g[k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
             s_h[k] = make_float4(q.z, q.w, r.c.x, r.c.y);
             s_b[k] = r.c.z;
-            s_r[k] = a.rect[id];
         }
         __syncthreads();
         if (!all_done) {
             for (int k = 0; k < cnt; ++k) {
-                const int4 rr = s_r[k];
-                const bool miss = rr.z < wx0 || rr.x > wx1 || rr.w < wy0 || rr.y > wy1;
-                if (__builtin_amdgcn_readfirstlane((int)miss)) continue;
                 const float4 g = s_g[k];
                 const float4 h = s_h[k];
                 const float4 q = make_float4(g.z, g.w, h.x, h.y);
@@ -153,12 +120,12 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
                 if constexpr (PPT == 1) {
                     // one pixel: branch, so a wavefront skips the blend when no lane takes it
                     const float e = exp2_at(q, A, B, fy[0] - g.y);
-                    const float alpha = fminf(amax, q.w * __builtin_amdgcn_exp2f(e));
+                    const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
                     if (alpha < amin) continue;
-                    const float test = T[0] * (1.0f - alpha);
+                    const float test = after(T[0], alpha);
                     if (test < tmin) {
                         done[0] = true;
-                        stop[0] = pos;
+                        if constexpr (COUNT) stop[0] = pos;
                         all_done = true;
                         break;
                     }
@@ -175,8 +142,8 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
 #pragma unroll
                     for (int p = 0; p < PPT; ++p) {
                         const float e = exp2_at(q, A, B, fy[p] - g.y);
-                        const float alpha = fminf(amax, q.w * __builtin_amdgcn_exp2f(e));
-                        const float test = T[p] * (1.0f - alpha);
+                        const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
+                        const float test = after(T[p], alpha);
                         const bool take = !done[p] && alpha >= amin;
                         const bool stp = take && test < tmin;
                         const bool use = take && !stp;
@@ -186,7 +153,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
                         C2[p] = fmaf(cb, w, C2[p]);
                         T[p] = use ? test : T[p];
                         last[p] = use ? pos : last[p];
-                        stop[p] = stp ? pos : stop[p];
+                        if constexpr (COUNT) stop[p] = stp ? pos : stop[p];
                         done[p] = done[p] || stp;
                         left = left || !done[p];
                     }
@@ -214,7 +181,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
             evaluated += stop[p];
         }
     }
-    if (a.pairs) {
+    if constexpr (COUNT) {
         const unsigned long long w = wave_sum((unsigned long long)evaluated);
         if (lane_id() == 0) atomicAdd(a.pairs, w);
     }
@@ -247,6 +214,7 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
     __shared__ float4 s_cn[BATCH];    // staged conic and opacity, as in the forward
     __shared__ float4 s_rgb[BATCH];
     __shared__ uint32_t s_id[BATCH];
+    __shared__ float s_io[BATCH];     // 1 / opacity
     const int tile = blockIdx.x;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
@@ -289,6 +257,7 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
             s_cn[k] = staged_conic(r);
             s_rgb[k] = r.c;
             s_id[k] = id;
+            s_io[k] = 1.0f / r.b.w;
         }
         __syncthreads();
         for (int k = cnt - 1; k >= 0; --k) {
@@ -300,8 +269,7 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
                 const float2 c = s_xy[k];
                 const float4 q = s_cn[k];
                 const float dx = fx - c.x, dy = fy - c.y;
-                const float G = __builtin_amdgcn_exp2f(gauss_exp2(q, dx, dy));
-                const float raw = q.w * G;
+                const float raw = __builtin_amdgcn_exp2f(gauss_exp2(q, dx, dy));   // opacity x G
                 const float alpha = fminf(amax, raw);
                 if (alpha >= amin) {
                     hit = true;
@@ -318,8 +286,8 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
                     S1 += col.y * w;
                     S2 += col.z * w;
                     if (raw < amax) {
-                        // power = -1/2 (a dx^2 + 2 b dx dy + c dy^2) = ln2 * exponent
-                        dop = G * dalpha;
+                        // power = -1/2 (a dx^2 + 2 b dx dy + c dy^2); alpha = opacity exp(power)
+                        dop = raw * s_io[k] * dalpha;                 // G = raw / opacity
                         const float dpow = alpha * dalpha;   // d alpha / d power
                         da = -0.5f * dx * dx * dpow;
                         db = -dx * dy * dpow;
@@ -358,8 +326,10 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
 
 template <int TW, int TH, int BATCH, int PPT>
 void launch_fwd_ppt(const CompArgs &a, int n_tiles, hipStream_t s) {
-    static_assert(PPT > 1 || (TW % 8 == 0 && TH % 8 == 0), "8x8 blocks per wavefront");
-    hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
+    if (a.pairs)
+        hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT, true>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
+    else
+        hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT, false>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
 }
 
 // Pixels per thread: 1 for 8x8 tiles (one wavefront per tile), a.ppt (1, 2
@@ -413,7 +383,7 @@ hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_
                             uint64_t *pair_counter, int32_t ppt, hipStream_t s) {
     if (ppt != 1 && ppt != 2 && ppt != 4) return hipErrorInvalidValue;
     CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, n_contrib,
-               reinterpret_cast<unsigned long long *>(pair_counter), ppt, V, reinterpret_cast<const int4 *>(rect)};
+               reinterpret_cast<unsigned long long *>(pair_counter), ppt, V};
     const int n_tiles = rp.tiles_x * rp.tiles_y * V;
     FDGS_DISPATCH(launch_fwd, a);
     return hipGetLastError();
