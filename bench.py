@@ -197,9 +197,15 @@ def fwd_bwd(ctx, steps, warmup):
         step()
     sync()
     dt = time.perf_counter() - t0
+    ctx.profile(True)
+    for _ in range(3):
+        step()
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    stage_ms = {k: round(v / 3, 4) for k, v in prof["ms"].items() if v > 0}
     for s in states:
         ctx.release(s)
-    return dt * 1e3 / steps, views
+    return dt * 1e3 / steps, views, stage_ms
 
 
 def batched(ctx, steps=3):
@@ -415,8 +421,9 @@ def main():
 
         # ---- forward + backward ------------------------------------------------------
         log("[bench] fwd+bwd: 500k Gaussians, 4 views")
-        ms_iter, views = fwd_bwd(ctx, 20, 5)
+        ms_iter, views, fb_stages = fwd_bwd(ctx, 20, 5)
         extra["fwd_bwd_ms_per_iter"] = round(ms_iter, 3)
+        extra["fwd_bwd_stage_ms_per_iter"] = fb_stages
         extra["fwd_bwd_config"] = {"gaussians": 500_000, "views": views, "resolution": [W, H],
                                    "loss": "0.5*sum((I-I*)^2), targets rendered from a second seed"}
         log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter")

@@ -289,10 +289,9 @@ FDGS_API fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int3
 /*
  * Reports FDGS_ERR_CAPACITY if a forward with a fixed instance_capacity on
  * this context overflowed since the last check, or FDGS_ERR_UNSUPPORTED if
- * more than 4096 visible Gaussians of one forward had depths within a relative
- * 2^-15 of each other (their relative order then falls back to processing
- * order instead of the float64 depth); clears the flags.  Synchronises
- * `stream`.
+ * more than 4096 visible Gaussians of one forward shared a float32-rounded
+ * depth (their relative order then falls back to processing order instead of
+ * the float64 depth); clears the flags.  Synchronises `stream`.
  */
 FDGS_API fdgs_status fdgs_check_overflow(fdgs_ctx *ctx, hipStream_t stream);
 

@@ -485,7 +485,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
         StageTimer tm(ctx, FDGS_STAGE_DEPTH_SORT, stream);
         int alt = 0;
         HIP_TRY(radix_sort_u32(S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->order_k2.as<uint32_t>(),
-                               S->order_v2.as<uint32_t>(), counts + 0, n_max, 0, 24, S->scratch.p, &alt, stream));
+                               S->order_v2.as<uint32_t>(), counts + 0, n_max, 0, 32, S->scratch.p, &alt, stream));
         uint32_t *ok = alt ? S->order_k2.as<uint32_t>() : S->order_k.as<uint32_t>();
         ov = alt ? S->order_v2.as<uint32_t>() : S->order_v.as<uint32_t>();
         HIP_TRY(launch_fix_depth_ties(ok, ov, S->depth_key.as<uint64_t>(), counts + 0, n_max,
@@ -965,7 +965,7 @@ fdgs_status fdgs_check_overflow(fdgs_ctx *ctx, hipStream_t stream) {
         if (flag & 1)
             return fail(FDGS_ERR_CAPACITY, "fdgs_check_overflow: a forward pass exceeded its instance capacity");
         return fail(FDGS_ERR_UNSUPPORTED,
-                    "fdgs_check_overflow: more than 4096 Gaussians had depths within 2^-15 of each other; "
+                    "fdgs_check_overflow: more than 4096 Gaussians shared one float32 depth; "
                     "their order fell back to processing order");
     }
     return FDGS_OK;

@@ -28,6 +28,25 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Sum over the 64 lanes with DPP row operations (no LDS traffic); the total
+// is valid in lane 63.  Steps: xor-1 and xor-2 inside quads, half-row mirror,
+// row mirror (every lane now holds its 16-lane row sum), then row broadcasts
+// 15 and 31 fold rows 0..3 into row 3.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_add_c(float v) {
+    const int o = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, true);
+    return v + __builtin_bit_cast(float, o);
+}
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+    v = dpp_add_c<0xB1>(v);          // quad_perm(1,0,3,2)
+    v = dpp_add_c<0x4E>(v);          // quad_perm(2,3,0,1)
+    v = dpp_add_c<0x141>(v);         // row_half_mirror
+    v = dpp_add_c<0x140>(v);         // row_mirror
+    v = dpp_add_c<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_add_c<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Exclusive sum over a block of NT threads (NT a multiple of 64, <= 1024).
 // `tmp` must hold NT/64 + 1 elements of shared memory.  Returns the thread's
 // exclusive prefix; *total receives the block total.  Contains barriers.

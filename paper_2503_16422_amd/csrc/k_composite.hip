@@ -215,6 +215,7 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
     __shared__ float4 s_rgb[BATCH];
     __shared__ uint32_t s_id[BATCH];
     __shared__ float s_io[BATCH];     // 1 / opacity
+    __shared__ float s_acc[BATCH * 9]; // per-Gaussian gradient sums of the tile
     const int tile = blockIdx.x;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
@@ -246,6 +247,7 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
     __syncthreads();
     const uint32_t walk_end = start + s_max;
     const int lane = lane_id();
+    for (int j = threadIdx.x; j < BATCH * 9; j += NT) s_acc[j] = 0.0f;
     for (int64_t top = (int64_t)walk_end; top > (int64_t)start; top -= BATCH) {
         const uint32_t lo = (uint32_t)max((int64_t)start, top - BATCH);
         const int cnt = (int)(top - lo);
@@ -298,28 +300,36 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
                 }
             }
             if (__ballot(hit) != 0ull) {
-                du = wave_sum(du);
-                dv = wave_sum(dv);
-                da = wave_sum(da);
-                db = wave_sum(db);
-                dc = wave_sum(dc);
-                dop = wave_sum(dop);
-                dr = wave_sum(dr);
-                dg = wave_sum(dg);
-                dbl = wave_sum(dbl);
-                if (lane == 0) {
-                    float *o = a.g2d + (int64_t)s_id[k] * 9;
-                    atomicAdd(o + 0, du);
-                    atomicAdd(o + 1, dv);
-                    atomicAdd(o + 2, da);
-                    atomicAdd(o + 3, db);
-                    atomicAdd(o + 4, dc);
-                    atomicAdd(o + 5, dop);
-                    atomicAdd(o + 6, dr);
-                    atomicAdd(o + 7, dg);
-                    atomicAdd(o + 8, dbl);
+                // wave sums (DPP, total in lane 63), then one LDS add per wave
+                du = wave_sum_to_last(du);
+                dv = wave_sum_to_last(dv);
+                da = wave_sum_to_last(da);
+                db = wave_sum_to_last(db);
+                dc = wave_sum_to_last(dc);
+                dop = wave_sum_to_last(dop);
+                dr = wave_sum_to_last(dr);
+                dg = wave_sum_to_last(dg);
+                dbl = wave_sum_to_last(dbl);
+                if (lane == 63) {
+                    float *acc = s_acc + k * 9;
+                    atomicAdd(acc + 0, du);
+                    atomicAdd(acc + 1, dv);
+                    atomicAdd(acc + 2, da);
+                    atomicAdd(acc + 3, db);
+                    atomicAdd(acc + 4, dc);
+                    atomicAdd(acc + 5, dop);
+                    atomicAdd(acc + 6, dr);
+                    atomicAdd(acc + 7, dg);
+                    atomicAdd(acc + 8, dbl);
                 }
             }
+        }
+        __syncthreads();
+        // one global add per (Gaussian, value) for the whole tile
+        for (int j = threadIdx.x; j < cnt * 9; j += NT) {
+            const float v = s_acc[j];
+            if (v != 0.0f) atomicAdd(a.g2d + (int64_t)s_id[j / 9] * 9 + (j % 9), v);
+            s_acc[j] = 0.0f;
         }
     }
 }

@@ -102,7 +102,7 @@ hipError_t scan_impl(Load ld, Out *out, const int64_t *n_dev, int64_t n_max, int
 }
 
 // Visible compaction: the downsweep of a scan over the visible flags that
-// writes each visible entry's (coarse depth key, position) to its slot.
+// writes each visible entry's (float32 depth bits, position) to its slot.
 __global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *visible, const uint64_t *depth_key,
                                                               const int64_t *n_dev, int64_t n_max,
                                                               const uint64_t *partial, uint32_t *keys32,
@@ -123,9 +123,7 @@ __global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *vis
     for (int k = 0; k < kItems; ++k) {
         if (v[k]) {
             const double z = __longlong_as_double((long long)depth_key[base + k]);
-            // z > 0: float bit order = value order; dropping 8 mantissa bits
-            // keeps it monotone (a 24-bit key: three 8-bit radix passes)
-            keys32[run] = __float_as_uint((float)z) >> 8;
+            keys32[run] = __float_as_uint((float)z);   // z > 0: bit order = value order
             vals[run] = (uint32_t)(base + k);
             ++run;
         }

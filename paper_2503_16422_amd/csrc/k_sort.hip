@@ -3,12 +3,11 @@
 // Gaussians, exact float64 depth order, tile-key duplication and tile ranges.
 //
 // Depth order (Eq. 2 blends "sorted by depth"): the visible Gaussians are
-// sorted by a 24-bit monotone key (the float32-rounded depth without its 8
-// low mantissa bits: 3 digit passes over N_vis, stable, so equal keys stay in
-// processing order), and runs of equal keys, which are short (depths within
-// 2^-15 relative), are then re-ordered by the float64 depth and the
-// processing position.  The key is monotone in the depth, so the result is
-// the order by (float64 depth, position).
+// sorted by the float32-rounded depth (4 digit passes over N_vis, stable, so
+// equal keys stay in processing order), and runs of equal float32 keys, which
+// are rare and short, are then re-ordered by the float64 depth and the
+// processing position.  Rounding is monotone, so the result is the order by
+// (float64 depth, position).
 //
 // Tile binning: instances are emitted in that depth order and then sorted
 // stably by tile id alone (ceil(tile_bits / 8) passes over the instances),
@@ -173,10 +172,10 @@ __global__ void scatter_visible_kernel(const uint8_t *visible, const uint32_t *p
     vals[pos[i]] = (uint32_t)i;
 }
 
-// Runs of equal coarse depth keys: insertion sort by (float64 depth, position).
-// Runs longer than kMaxTieRun (many Gaussians within 2^-15 relative depth,
-// which only constructed inputs produce) are left in processing order and
-// reported through *flag, bounding the work of one thread.
+// Runs of equal float32 depth keys: insertion sort by (float64 depth, position).
+// Runs longer than kMaxTieRun (many Gaussians at one depth to float32
+// precision, which only constructed inputs produce) are left in processing
+// order and reported through *flag, bounding the work of one thread.
 constexpr int64_t kMaxTieRun = 4096;
 
 __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t *depth_key,
