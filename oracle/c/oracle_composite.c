@@ -21,6 +21,12 @@
  * 2 a transmittance test within rel_t of t_min, 4 two consecutive
  * contributors whose depths differ, but by at most rel_depth * depth (exactly
  * equal depths are ordered by index, which is not ambiguous).
+ *
+ * Contributions (optional, per Gaussian, OR-ed over pixels): 1 blended at a
+ * pixel whose flags were still 0 after this Gaussian's own decisions (a float32
+ * renderer takes the same decisions, so it blends it too); 2 blended at some
+ * pixel, or reaching alpha >= alpha_min (1 - rel_alpha) anywhere in the list of
+ * a pixel that ends flagged (a float32 renderer may blend it there).
  */
 #include <math.h>
 #include <stdint.h>
@@ -30,6 +36,7 @@ typedef struct {
     int64_t n;
     const double *u, *v, *ca, *cb, *cc, *opac, *rgb, *depth; /* rgb: n x 3 */
     const int32_t *rect;                                     /* n x 4 (x0,y0,x1,y1) or NULL */
+    int32_t *contrib;                                        /* n, OR-ed contribution bits, or NULL */
     double bg[3];
     double alpha_min, alpha_max, t_min;
     double rel_alpha, rel_t, rel_depth;
@@ -63,11 +70,33 @@ static void shade_pixel(const oracle_scene *s, const int64_t *list, int64_t nlis
             if (gap > 0.0 && gap <= s->rel_depth * fabs(s->depth[i])) flag |= 4;
         }
         prev_depth = s->depth[i];
+        if (s->contrib) {
+            const int32_t bits = flag == 0 ? 3 : 2;
+            #pragma omp atomic update
+            s->contrib[i] |= bits;
+        }
         const double w = alpha * T;
         C0 += s->rgb[3 * i + 0] * w;
         C1 += s->rgb[3 * i + 1] * w;
         C2 += s->rgb[3 * i + 2] * w;
         T = test;
+    }
+    if (s->contrib && flag != 0) {
+        /* a flagged pixel: any Gaussian near or above alpha_min may be blended by a float32 walk */
+        for (int64_t k = 0; k < nlist; ++k) {
+            const int64_t i = list[k];
+            if (s->rect) {
+                const int32_t *r = s->rect + 4 * i;
+                if (px < r[0] || px > r[2] || py < r[1] || py > r[3]) continue;
+            }
+            const double dx = sx - s->u[i], dy = sy - s->v[i];
+            const double power = -0.5 * (s->ca[i] * dx * dx + 2.0 * s->cb[i] * dx * dy + s->cc[i] * dy * dy);
+            const double alpha = s->opac[i] * exp(power);
+            if (alpha >= s->alpha_min * (1.0 - s->rel_alpha)) {
+                #pragma omp atomic update
+                s->contrib[i] |= 2;
+            }
+        }
     }
     out_rgb[0] = C0 + T * s->bg[0];
     out_rgb[1] = C1 + T * s->bg[1];

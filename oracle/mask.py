@@ -16,6 +16,13 @@ set from training-view visibility; the predicates computed here are:
       Mahalanobis level 2 ln 255, as in `composite.pixel_rects` with culling
       off) covers at least one pixel of at least one mask view.
 
+  CONTRIBUTED (mode 2): the paper's keyframe visibility: keep Gaussian i iff
+      it is blended (Eq. 2: alpha >= alpha_min and the pixel's walk has not
+      stopped) at some pixel of some mask view rendered at key_lo or at
+      key_hi; the window's set is the union over views and both keyframes.
+      The window's frame times are not used.  Rendering a keyframe from a
+      mask view with this set gives exactly the unmasked image.
+
 Output: LSB-first bit words and the ascending kept indices.
 """
 from __future__ import annotations
@@ -24,12 +31,13 @@ import math
 
 import numpy as np
 
-from .composite import Settings, pixel_rects
+from .composite import Settings, composite, pixel_rects, prepare
 from .projection import project
 from .slicing import covariance_4d, rows, slice_at, valid_gaussians
 
 TEMPORAL = 0
 TEMPORAL_AND_TILE = 1
+CONTRIBUTED = 2
 
 
 def temporal_keep(mean_t: np.ndarray, sigma44: np.ndarray, frame_times, alpha_min=1.0 / 255.0):
@@ -57,6 +65,22 @@ def spatial_keep(scene_arrays, views, key_times, dilation: float = 0.3,
             r = pixel_rects(uv, cov2d, np.ones(M.shape[0]), cam.width, cam.height, st)
             keep |= ok & (r[:, 0] <= r[:, 2]) & (r[:, 1] <= r[:, 3])
     return keep & valid
+
+
+def contributed_keep(scene_arrays, views, key_times, st: Settings):
+    """(sure, maybe) bool[n]: blended at some pixel of some view at some key
+    time, with every decision on the way clear of the thresholds (sure), or
+    blended or possibly blended by a float32 walk (maybe)."""
+    n = scene_arrays[0].shape[1]
+    sure = np.zeros(n, dtype=bool)
+    maybe = np.zeros(n, dtype=bool)
+    for tk in key_times:
+        for cam in views:
+            pre = prepare(scene_arrays, cam, float(tk), st)
+            c = composite(pre, cam, st, mode="rect", contributions=True).contrib
+            sure |= (c & 1) != 0
+            maybe |= (c & 2) != 0
+    return sure, maybe
 
 
 def active_mask(scene_arrays, frame_times, key_lo: float, key_hi: float, mode: int = TEMPORAL,

@@ -366,6 +366,64 @@ def test_temporal_mask_render_equals_dense_and_bits():
     assert np.allclose(pmax, np.exp(-(near - mt) ** 2 / (2 * s44)))
 
 
+def test_contributed_mask_reproduces_keyframe_images_and_only_contributors():
+    """CONTRIBUTED keeps exactly the Gaussians a keyframe render blends: the
+    masked render of a mask view at a keyframe equals the dense one, removing
+    a surely blended Gaussian changes it, and the set lies inside the
+    temporal-and-footprint set."""
+    sc = inputs.tiny_scene(3000, seed=11)
+    sc.log_scale[:3] += 0.8
+    views = [inputs.look_at_camera(phi, 3.0, 48, 40) for phi in (-30.0, 25.0)]
+    st = oc.Settings()
+    t_lo, t_hi = 0.4, 0.45
+    sure, maybe = mask.contributed_keep(sc.arrays(), views, (t_lo, t_hi), st)
+    assert np.all(maybe[sure]) and 0 < sure.sum() <= maybe.sum() < sc.n
+    idx = np.flatnonzero(maybe)
+    for tk in (t_lo, t_hi):
+        for cam in views:
+            dense = oc.render(sc.arrays(), cam, tk, st, mode="rect")
+            masked = oc.render(sc.arrays(), cam, tk, st, mode="rect", idx=idx)
+            assert np.array_equal(dense.rgb, masked.rgb) and np.array_equal(dense.T, masked.T)
+    # each of a sample of surely blended Gaussians changes some keyframe image when removed
+    rng = np.random.default_rng(0)
+    for g in rng.choice(np.flatnonzero(sure), 6, replace=False):
+        rest = np.setdiff1d(np.arange(sc.n), [g])
+        changed = False
+        for tk in (t_lo, t_hi):
+            for cam in views:
+                a = oc.render(sc.arrays(), cam, tk, st, mode="rect")
+                b = oc.render(sc.arrays(), cam, tk, st, mode="rect", idx=rest)
+                changed = changed or not np.array_equal(a.rgb, b.rgb)
+        assert changed, g
+    keep1, _, _ = mask.active_mask(sc.arrays(), [t_lo, t_hi], t_lo, t_hi, mask.TEMPORAL_AND_TILE, views=views)
+    assert np.all(keep1[maybe])
+
+
+def test_contributed_mask_drops_occluded_gaussians():
+    """Behind five large Gaussians of opacity 0.95 (T < t_min after at most
+    five of them at every pixel) nothing is blended: the hidden Gaussian is
+    dropped although its footprint covers the view."""
+    sc = inputs.tiny_scene(6, seed=1)
+    cam = inputs.look_at_camera(0.0, 3.0, 32, 32)
+    C = -cam.R.T @ cam.tvec                      # camera centre; the view axis points to the origin
+    fwd = -C / np.linalg.norm(C)
+    for i, dist in enumerate((1.0, 1.1, 1.2, 1.3, 1.4, 2.5)):
+        sc.mean[:3, i] = (C + dist * fwd).astype(np.float32)
+        sc.mean[3, i] = 0.5
+        sc.log_scale[:3, i] = np.log(2.0 if i < 5 else 0.05)
+        sc.log_scale[3, i] = np.log(5.0)
+        sc.opacity_logit[i] = math.log(0.95 / 0.05)
+    sc.q_left[:, :] = np.array([[1.0], [0.0], [0.0], [0.0]], dtype=np.float32)
+    sc.q_right[:, :] = sc.q_left
+    st = oc.Settings()
+    img = oc.render(sc.arrays(), cam, 0.5, st, mode="brute")
+    assert not img.flags.any()
+    sure, maybe = mask.contributed_keep(sc.arrays(), [cam], (0.5,), st)
+    assert sure[0] and sure[1] and not maybe[5]
+    keep1, _, _ = mask.active_mask(sc.arrays(), [0.5], 0.5, 0.5, mask.TEMPORAL_AND_TILE, views=[cam])
+    assert keep1[5]
+
+
 def test_tile_mask_is_subset_and_keeps_what_is_seen_at_keyframes():
     sc = inputs.long_scene(3000, seed=4)
     views = inputs.arc_cameras(3, 4.0, 64, 48)
@@ -414,6 +472,65 @@ def test_binning_invariants_and_rect_brute_force():
             hy = math.sqrt(q[i] * pre.cov2d[i, 1, 1])
             box = (np.abs(dx) <= hx) & (np.abs(dy) <= hy)
             assert np.array_equal(box, inside)
+
+
+def test_reached_tiles_of_circles_closed_form_and_subset_of_rectangles():
+    """An isotropic ellipse (conic = I / s^2) reaches a tile iff the tile's
+    pixel centre nearest to (u, v) lies within sqrt(q) s; the nearest centre
+    is the clamp of (u, v) to the tile's centre grid.  Reached pairs are a
+    subset of the rectangle's tiles, and pixels reaching alpha_min lie in
+    reached tiles."""
+    rng = np.random.default_rng(4)
+    W, H, TW, TH = 97, 70, 16, 8
+    n = 300
+    uv = np.stack([rng.uniform(-10, W + 10, n), rng.uniform(-10, H + 10, n)], axis=1)
+    s = np.exp(rng.uniform(np.log(0.3), np.log(12.0), n))
+    conic = np.stack([1 / s ** 2, np.zeros(n), 1 / s ** 2], axis=1)
+    cov = np.zeros((n, 2, 2))
+    cov[:, 0, 0] = cov[:, 1, 1] = s ** 2
+    opac = rng.uniform(0.005, 1.0, n)
+    st = oc.Settings()
+    rect = oc.pixel_rects(uv, cov, opac, W, H, st)
+    visible = (rect[:, 0] <= rect[:, 2]) & (rect[:, 1] <= rect[:, 3])
+    q = oc.cut_level(opac, st)
+    got = binning.reached_pairs(rect, uv, conic, q, visible, W, TW, TH)
+    tiles_x = (W + TW - 1) // TW
+    want = []
+    for i in np.flatnonzero(visible):
+        x0, y0, x1, y1 = rect[i]
+        for ty in range(y0 // TH, y1 // TH + 1):
+            for tx in range(x0 // TW, x1 // TW + 1):
+                cx0, cx1 = max(tx * TW, x0), min(tx * TW + TW - 1, x1)
+                cy0, cy1 = max(ty * TH, y0), min(ty * TH + TH - 1, y1)
+                px = min(max(math.floor(uv[i, 0]), cx0), cx1)     # centre px + 0.5 nearest to u
+                py = min(max(math.floor(uv[i, 1]), cy0), cy1)
+                if (px + 0.5 - uv[i, 0]) ** 2 + (py + 0.5 - uv[i, 1]) ** 2 <= q[i] * s[i] ** 2:
+                    want.append((ty * tiles_x + tx) * n + i)
+    assert np.array_equal(got, np.sort(np.asarray(want, dtype=np.int64)))
+    ids, tiles, _ = binning.bin_gaussians(rect, np.arange(n, dtype=float), visible, W, H, TW, TH)
+    assert np.all(np.isin(got, tiles * n + ids.astype(np.int64)))
+
+
+def test_reached_tiles_of_a_thin_diagonal_ellipse():
+    """A long ellipse along the image diagonal reaches the diagonal tiles and
+    far fewer tiles than its bounding rectangle covers."""
+    W = H = 256
+    L, w = 80.0, 0.6                                    # std along / across the diagonal
+    R = np.array([[1, -1], [1, 1]]) / math.sqrt(2)
+    cov = R @ np.diag([L ** 2, w ** 2]) @ R.T
+    ic = np.linalg.inv(cov)
+    uv = np.array([[128.0, 128.0]])
+    st = oc.Settings()
+    rect = oc.pixel_rects(uv, cov[None], np.array([0.9]), W, H, st)
+    q = oc.cut_level(np.array([0.9]), st)
+    got = binning.reached_pairs(rect, uv, np.array([[ic[0, 0], ic[0, 1], ic[1, 1]]]), q, np.array([True]),
+                                W, 16, 16)
+    tiles = got // 1
+    x0, y0, x1, y1 = rect[0]
+    n_rect = (x1 // 16 - x0 // 16 + 1) * (y1 // 16 - y0 // 16 + 1)
+    assert n_rect == 256 and tiles.size < 0.25 * n_rect
+    diag = np.arange(16) * 16 + np.arange(16)
+    assert np.all(np.isin(diag, tiles))
 
 
 # P-14 gradients ------------------------------------------------------------------------------
