@@ -243,7 +243,7 @@ def batched(ctx, steps=3):
     per = 128
     best, sweep = ctx.autotune(models, views[:64], _lib.default_cfg(), views_per_launch=64, repeats=2)
     cfg = _lib.default_cfg(tile_w=best.tile_w, tile_h=best.tile_h, batch=best.batch,
-                           pixels_per_thread=best.pixels_per_thread)
+                           pixels_per_thread=best.pixels_per_thread, schedule=best.schedule)
     out = torch.empty((len(views), 3, 800, 800), dtype=torch.float32, device="cuda")
     ctx.profile(True)
     ctx.render_batch(models, views, cfg, views_per_launch=per, out=out)
@@ -270,8 +270,8 @@ def batched(ctx, steps=3):
             "graph_ms_per_batch": round(dt * 1e3, 2), "views_per_s": round(len(views) / dt, 1),
             "instances_per_view": int(prof["instances"] / len(views)),
             "autotuned": {"tile": [best.tile_w, best.tile_h], "batch": best.batch,
-                          "pixels_per_thread": best.pixels_per_thread},
-            "autotune_sweep_ms_64_views": {f"{r['tile'][0]}x{r['tile'][1]}/b{r['batch']}/p{r['pixels_per_thread']}":
+                          "pixels_per_thread": best.pixels_per_thread, "schedule": best.schedule},
+            "autotune_sweep_ms_64_views": {f"{r['tile'][0]}x{r['tile'][1]}/b{r['batch']}/p{r['pixels_per_thread']}/s{r['schedule']}":
                                            round(r["ms"], 3) for r in sweep},
             "setup_s": round(setup_s, 2)}
 
@@ -285,7 +285,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the masked headline loop (for profiler runs)")
     ap.add_argument("--config", default=None,
-                    help="tile_w,tile_h,batch,pixels_per_thread: skip the autotuner and use this configuration")
+                    help="tile_w,tile_h,batch,pixels_per_thread,schedule: skip the autotuner and use this "
+                         "configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -326,12 +327,12 @@ def main():
         idx, cnt = masks[frame_window[f]]
         tune_views.append((0, cams[c], float(frames[f]), idx, int(cnt.item())))
     if args.config:
-        tw, th, b, p = (int(x) for x in args.config.split(","))
-        tuned, sweep = dict(tile_w=tw, tile_h=th, batch=b, pixels_per_thread=p), []
+        tw, th, b, p, sc = (int(x) for x in args.config.split(","))
+        tuned, sweep = dict(tile_w=tw, tile_h=th, batch=b, pixels_per_thread=p, schedule=sc), []
     else:
         best, sweep = ctx.autotune([model], tune_views, _lib.default_cfg(), views_per_launch=1, repeats=2)
         tuned = dict(tile_w=best.tile_w, tile_h=best.tile_h, batch=best.batch,
-                     pixels_per_thread=best.pixels_per_thread)
+                     pixels_per_thread=best.pixels_per_thread, schedule=best.schedule)
     log(f"[bench] autotuned {tuned}")
     worst = max_instances(ctx, model, cams, frames, masks, frame_window, _lib.default_cfg(**tuned), K + Wu, 0)
     log(f"[bench] max instances over the timed frames {worst}")
@@ -365,7 +366,8 @@ def main():
     comp["achieved_TFLOPs"] = round(comp_tflops, 3)
     dominant = max(stages, key=lambda s: stages[s]["avg_ms"])
     if dominant == "composite":
-        kname = f"composite_kernel<{cfg.tile_w},{cfg.tile_h},{cfg.batch},{cfg.pixels_per_thread}>"
+        kname = (f"composite_kernel<{cfg.tile_w},{cfg.tile_h},{cfg.batch},{cfg.pixels_per_thread},false,"
+                 f"{'true' if cfg.schedule else 'false'}>")
         roof = {"bound": "alu", "kernel": kname, "achieved": round(comp_tflops, 3),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(comp_tflops / FP32_PEAK_TFLOPS, 4),
                 "traffic": load_traffic("composite")}
@@ -388,6 +390,12 @@ def main():
                 f, _ = timed_fps(ctx, model, cams, frames, masks if use_mask else None, frame_window, c0,
                                  n_grid, 5, out, start=1000)
                 grid[f"mask={'on' if use_mask else 'off'},cull={'on' if cull else 'off'}"] = round(f, 1)
+        for use_mask in (True, False):
+            c0 = _lib.default_cfg(temporal_cull=int(use_mask), tile_cull=0)
+            f, _ = timed_fps(ctx, model, cams, frames, masks if use_mask else None, frame_window, c0,
+                             n_grid, 5, out, start=1000)
+            key = "mask=on,cull=on" if use_mask else "mask=off,cull=off"
+            grid[key + ",tile_cull=off"] = round(f, 1)
         log(f"[bench] grid: {grid}")
         extra["masked_scene_grid_fps"] = grid
 
@@ -399,14 +407,18 @@ def main():
         dmodel = GaussianModel.from_scene(dense, "cuda:0")
         del dense
         n_dense = 16
-        vanilla = _lib.default_cfg(temporal_cull=0)
+        vanilla = _lib.default_cfg(temporal_cull=0, tile_cull=0)
         d_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, vanilla, n_dense, 3, out, start=2000)
+        dt_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, _lib.default_cfg(temporal_cull=0),
+                              n_dense, 3, out, start=2000)
         dc_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, _lib.default_cfg(), n_dense, 3, out,
                               start=2000)
         dmasks, dfw, _, dmask_ms, dkept = build_masks(ctx, dmodel, cams)
         dm_fps, _ = timed_fps(ctx, dmodel, cams, frames, dmasks, dfw, _lib.default_cfg(), 60, 5, out, start=2000)
-        log(f"[bench] dense: vanilla {d_fps:.1f}, +cull {dc_fps:.1f}, +mask {dm_fps:.1f} frames/s")
-        extra["dense_3M"] = {"vanilla_fps": round(d_fps, 2), "temporal_cull_fps": round(dc_fps, 2),
+        log(f"[bench] dense: vanilla {d_fps:.1f}, +tile cull {dt_fps:.1f}, +temporal cull {dc_fps:.1f}, "
+            f"+mask {dm_fps:.1f} frames/s")
+        extra["dense_3M"] = {"vanilla_fps": round(d_fps, 2), "vanilla_tile_cull_fps": round(dt_fps, 2),
+                             "temporal_cull_fps": round(dc_fps, 2),
                              "masked_fps": round(dm_fps, 2), "mask_build_ms_per_window": round(dmask_ms, 2),
                              "kept_mean": int(np.mean(dkept))}
         extra["masked_200k_vs_dense_3M_vanilla"] = round(fps / d_fps, 2)
@@ -449,7 +461,7 @@ def main():
                                "(temporal and tile predicate)",
                    "autotuned": tuned, "default_config_fps": round(fps_default, 2),
                    "autotune_sweep_ms_per_frame": {
-                       f"{r['tile'][0]}x{r['tile'][1]}/b{r['batch']}/p{r['pixels_per_thread']}":
+                       f"{r['tile'][0]}x{r['tile'][1]}/b{r['batch']}/p{r['pixels_per_thread']}/s{r['schedule']}":
                        round(r["ms"] / len(tune_views), 4) for r in sweep},
                    "gaussians": 200_000, "resolution": [W, H], "mask_windows": len(masks),
                    "kept_per_window_mean": int(np.mean(kept)), "per_frame": per_frame,

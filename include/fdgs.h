@@ -111,6 +111,14 @@ typedef struct {
     int32_t temporal_cull;      /* 1: drop sigma*p(t) < alpha_min before binning;
                                    0: bin every Gaussian in view (the
                                    unfiltered baseline's work)            [1] */
+    int32_t tile_cull;          /* 1: list a Gaussian only in the tiles of its
+                                   rectangle that its footprint ellipse
+                                   reaches; 0: in every tile of the
+                                   rectangle.  The image is the same     [1] */
+    int32_t schedule;           /* compositor schedule: 0 one workgroup per
+                                   tile in raster order; 1 persistent
+                                   workgroups take (view, tile) items
+                                   longest list first.  Same image        [0] */
     int64_t instance_capacity;  /* 0: size tile-list buffers exactly (one
                                    host synchronisation per frame); >0: fixed
                                    capacity, no synchronisation, overflow
@@ -145,21 +153,28 @@ FDGS_API fdgs_status fdgs_slice_4d(fdgs_ctx *ctx, const fdgs_model *model, doubl
  *   mode FDGS_MASK_TEMPORAL_AND_TILE: additionally keep only Gaussians whose
  *     opacity-free footprint (level 2 ln(1/alpha_min)) covers a pixel of one of
  *     the mask views at key_lo or key_hi.
+ *   mode FDGS_MASK_CONTRIBUTED (the keyframe visibility of Sec. 4.2.2): render
+ *     every mask view at key_lo and at key_hi (all n Gaussians, default
+ *     render options with this alpha_min and dilation) and keep Gaussian i iff
+ *     some pixel blends it (Eq. 2: alpha >= alpha_min before the pixel's walk
+ *     stops); the set is the union over views and both keyframes.  Frame
+ *     times are not used (n_frames may be 0).  Rendering a keyframe from a
+ *     mask view with this set gives exactly the unmasked image.
  * Outputs (device): out_bits[ceil(n/32)] (bit i%32 of word i/32, LSB first),
  * out_idx[n] (kept indices ascending; entries past the count are unspecified)
  * and *out_count (int64).  Synchronises `stream` (the host arrays of the spec
  * are copied to the device during the call).
  */
-enum { FDGS_MASK_TEMPORAL = 0, FDGS_MASK_TEMPORAL_AND_TILE = 1 };
+enum { FDGS_MASK_TEMPORAL = 0, FDGS_MASK_TEMPORAL_AND_TILE = 1, FDGS_MASK_CONTRIBUTED = 2 };
 typedef struct {
-    const double *frame_times;  /* host, n_frames >= 1 (<= 256)              */
+    const double *frame_times;  /* host, 1 <= n_frames <= 256 (modes 0, 1)   */
     int32_t n_frames;
-    const fdgs_camera *views;   /* host, n_views mask views (mode 1 only)     */
+    const fdgs_camera *views;   /* host, n_views mask views (modes 1, 2)      */
     int32_t n_views;            /* <= 64                                      */
     double key_lo, key_hi;      /* keyframe times of the window               */
     int32_t mode;
     float alpha_min;            /* threshold on p(t) [1/255 if <= 0]          */
-    float dilation;             /* footprint dilation (mode 1) [0.3 if < 0]   */
+    float dilation;             /* footprint dilation (modes 1, 2) [0.3 if < 0] */
 } fdgs_mask_spec;
 
 FDGS_API fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model,
@@ -266,8 +281,9 @@ FDGS_API fdgs_status fdgs_render_batch(fdgs_ctx *ctx, const fdgs_model *scenes, 
 
 /*
  * Autotuner: renders the batch with every tile shape (8x8, 16x16, 32x8), LDS
- * batch (64, 128, 256) and pixels-per-thread choice (1, 2, 4; 1 only for
- * 8x8), times each with HIP events (best of `repeats`), checks that every
+ * batch (64, 128, 256), pixels-per-thread choice (1, 2, 4; 1 only for 8x8)
+ * and compositor schedule (1, 0): 42 configurations, each timed with HIP
+ * events (best of `repeats`).  It checks that every
  * configuration's images are bit-identical to the first one's, and writes the
  * fastest into *inout_cfg (other fields are kept).  results (host, may be
  * NULL) receives up to max_results entries; *n_results the number tried.
@@ -275,7 +291,7 @@ FDGS_API fdgs_status fdgs_render_batch(fdgs_ctx *ctx, const fdgs_model *scenes, 
  * Synchronises `stream`.
  */
 typedef struct {
-    int32_t tile_w, tile_h, batch, pixels_per_thread;
+    int32_t tile_w, tile_h, batch, pixels_per_thread, schedule;
     double ms;
     int32_t identical;
 } fdgs_tune_result;

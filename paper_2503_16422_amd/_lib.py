@@ -20,6 +20,7 @@ FDGS_ERR_STATE = 5
 
 MASK_TEMPORAL = 0
 MASK_TEMPORAL_AND_TILE = 1
+MASK_CONTRIBUTED = 2
 
 EXPORTS = ["fdgs_last_error", "fdgs_version", "fdgs_create", "fdgs_destroy", "fdgs_render_cfg_default",
            "fdgs_slice_4d", "fdgs_build_active_mask", "fdgs_render_forward", "fdgs_render_backward",
@@ -48,7 +49,7 @@ class RenderCfg(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("pixels_per_thread", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float), ("temporal_cull", ctypes.c_int32),
-                ("instance_capacity", ctypes.c_int64)]
+                ("tile_cull", ctypes.c_int32), ("schedule", ctypes.c_int32), ("instance_capacity", ctypes.c_int64)]
 
 
 class MaskSpec(ctypes.Structure):
@@ -76,7 +77,8 @@ class View(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("pixels_per_thread", ctypes.c_int32), ("ms", ctypes.c_double), ("identical", ctypes.c_int32)]
+                ("pixels_per_thread", ctypes.c_int32), ("schedule", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("identical", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):

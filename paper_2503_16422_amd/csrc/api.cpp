@@ -92,6 +92,7 @@ struct fdgs_state {
     Buf tkeys, tids, tkeys2, tids2;
     // per tile / pixel
     Buf ranges, T_final, n_contrib;
+    Buf sched;         // uint32[V x tiles + 1]: persistent compositor order and work counter
     Buf counts;        // int64[4]: n_vis, n_inst
     Buf g2d;
     Buf scratch;
@@ -111,7 +112,7 @@ struct fdgs_state {
 
     void free_all() {
         for (Buf *b : {&rec, &depth_key, &rect, &tiles, &visible, &vis_pos, &order_k, &order_v, &order_k2,
-                       &order_v2, &offsets, &view_of, &tkeys, &tids, &tkeys2, &tids2, &ranges, &T_final,
+                       &order_v2, &offsets, &view_of, &tkeys, &tids, &tkeys2, &tids2, &ranges, &sched, &T_final,
                        &n_contrib, &counts, &g2d, &scratch})
             release(*b);
     }
@@ -128,6 +129,7 @@ struct fdgs_ctx {
     std::vector<fdgs_state *> states;
     Buf overflow;                  // int32 device flag
     Buf mask_frames, mask_views, mask_scratch;
+    Buf mask_flags, mask_img;      // contributed-mode visibility bytes and the keyframe image
     int64_t *host_counts = nullptr;  // pinned
     // profiling
     bool prof = false;
@@ -197,6 +199,8 @@ void fdgs_render_cfg_default(fdgs_render_cfg *cfg) {
     cfg->t_min = 1e-4f;
     cfg->dilation = 0.3f;
     cfg->temporal_cull = 1;
+    cfg->tile_cull = 1;
+    cfg->schedule = 0;
     cfg->instance_capacity = 0;
 }
 
@@ -246,6 +250,8 @@ fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
     release(ctx->mask_frames);
     release(ctx->mask_views);
     release(ctx->mask_scratch);
+    release(ctx->mask_flags);
+    release(ctx->mask_img);
     release(ctx->prof_acc);
     for (auto &p : ctx->pending) {
         (void)hipEventDestroy(p.e0);
@@ -337,6 +343,11 @@ fdgs_state *find_state(fdgs_ctx *ctx, fdgs_state *s) {
     return nullptr;
 }
 
+fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const ViewDesc *table, int32_t V,
+                        const int64_t *n_dev, int64_t n_total, int32_t W, int32_t H, const fdgs_render_cfg *cfg,
+                        float *out_rgb, float *out_T, bool need_state, hipStream_t stream,
+                        uint8_t *contrib = nullptr);
+
 }  // namespace
 
 extern "C" {
@@ -363,15 +374,20 @@ fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const
     if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
     if (fdgs_status st = check_model(model, fn)) return st;
     if (!spec) return fail(FDGS_ERR_INVALID_ARG, "%s: spec is NULL", fn);
-    if (spec->mode != FDGS_MASK_TEMPORAL && spec->mode != FDGS_MASK_TEMPORAL_AND_TILE)
+    if (spec->mode != FDGS_MASK_TEMPORAL && spec->mode != FDGS_MASK_TEMPORAL_AND_TILE &&
+        spec->mode != FDGS_MASK_CONTRIBUTED)
         return fail(FDGS_ERR_INVALID_ARG, "%s: unknown mode %d", fn, spec->mode);
-    if (spec->n_frames < 1 || spec->n_frames > 256 || !spec->frame_times)
-        return fail(FDGS_ERR_INVALID_ARG, "%s: need 1..256 frame times", fn);
-    for (int f = 0; f < spec->n_frames; ++f)
-        if (!std::isfinite(spec->frame_times[f])) return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite frame time", fn);
-    if (spec->mode == FDGS_MASK_TEMPORAL_AND_TILE) {
+    const bool contributed = spec->mode == FDGS_MASK_CONTRIBUTED;
+    if (!contributed) {
+        if (spec->n_frames < 1 || spec->n_frames > 256 || !spec->frame_times)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: need 1..256 frame times", fn);
+        for (int f = 0; f < spec->n_frames; ++f)
+            if (!std::isfinite(spec->frame_times[f]))
+                return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite frame time", fn);
+    }
+    if (spec->mode != FDGS_MASK_TEMPORAL) {
         if (spec->n_views < 1 || spec->n_views > 64 || !spec->views)
-            return fail(FDGS_ERR_INVALID_ARG, "%s: tile mode needs 1..64 views", fn);
+            return fail(FDGS_ERR_INVALID_ARG, "%s: modes 1 and 2 need 1..64 views", fn);
         for (int v = 0; v < spec->n_views; ++v)
             if (fdgs_status st = check_camera(&spec->views[v], fn)) return st;
         if (!std::isfinite(spec->key_lo) || !std::isfinite(spec->key_hi))
@@ -383,6 +399,42 @@ fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const
     const float dil = spec->dilation >= 0.0f ? spec->dilation : 0.3f;
     HIP_TRY(hipSetDevice(ctx->device));
     const int64_t n = model->n;
+    if (contributed) {
+        // the union over views and both keyframes of the Gaussians some pixel blends
+        fdgs_render_cfg cfg;
+        fdgs_render_cfg_default(&cfg);
+        cfg.alpha_min = amin;
+        cfg.dilation = dil;
+        cfg.pixels_per_thread = 2;
+        int64_t px_max = 1;
+        for (int v = 0; v < spec->n_views; ++v)
+            px_max = std::max<int64_t>(px_max, (int64_t)spec->views[v].width * spec->views[v].height);
+        HIP_TRY(ensure(ctx->mask_flags, (size_t)((n + 3) / 4) * 4 + 4));
+        HIP_TRY(ensure(ctx->mask_img, sizeof(float) * 3 * (size_t)px_max));
+        HIP_TRY(launch_fill_u32(ctx->mask_flags.as<uint32_t>(), (n + 3) / 4, 0u, stream));
+        const double keys[2] = {spec->key_lo, spec->key_hi};
+        for (int k = 0; k < (spec->key_hi == spec->key_lo ? 1 : 2); ++k) {
+            for (int v = 0; v < spec->n_views; ++v) {
+                ViewDesc one;
+                one.m = kmodel(model);
+                one.cam = kcam(&spec->views[v]);
+                one.t = keys[k];
+                one.idx = nullptr;
+                one.p_off = 0;
+                one.n_proc = n;
+                if (fdgs_status st = run_forward(ctx, &ctx->scratch_state, &one, nullptr, 1, nullptr, n,
+                                                 spec->views[v].width, spec->views[v].height, &cfg,
+                                                 ctx->mask_img.as<float>(), nullptr, false, stream,
+                                                 ctx->mask_flags.as<uint8_t>()))
+                    return st;
+            }
+        }
+        HIP_TRY(launch_flags_to_bits(ctx->mask_flags.as<uint8_t>(), n, out_bits, stream));
+        HIP_TRY(ensure(ctx->mask_scratch, compact_scratch_bytes(n)));
+        HIP_TRY(compact_bits(out_bits, n, out_idx, out_count, ctx->mask_scratch.p, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return FDGS_OK;
+    }
     HIP_TRY(ensure(ctx->mask_frames, sizeof(double) * spec->n_frames));
     HIP_TRY(hipMemcpyAsync(ctx->mask_frames.p, spec->frame_times, sizeof(double) * spec->n_frames,
                            hipMemcpyHostToDevice, stream));
@@ -428,6 +480,8 @@ RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
     rp.t_min = cfg->t_min;
     rp.dilation = cfg->dilation;
     rp.temporal_cull = cfg->temporal_cull ? 1 : 0;
+    rp.tile_cull = cfg->tile_cull ? 1 : 0;
+    rp.vanilla_level = 2.0 * std::log(1.0 / (double)cfg->alpha_min) * (1.0 + 1e-4) + 1e-4;
     return rp;
 }
 
@@ -438,7 +492,7 @@ RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
 // buffers are already large enough and a fixed instance capacity is given.
 fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const ViewDesc *table, int32_t V,
                         const int64_t *n_dev, int64_t n_total, int32_t W, int32_t H, const fdgs_render_cfg *cfg,
-                        float *out_rgb, float *out_T, bool need_state, hipStream_t stream) {
+                        float *out_rgb, float *out_T, bool need_state, hipStream_t stream, uint8_t *contrib) {
     const char *fn = "fdgs_render";
     const RenderParams rp = make_params(cfg, W, H);
     const int64_t tiles_per_view = (int64_t)rp.tiles_x * rp.tiles_y;
@@ -460,6 +514,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     if (V > 1) HIP_TRY(ensure(S->view_of, sizeof(uint32_t) * n_max));
     HIP_TRY(ensure(S->counts, sizeof(int64_t) * 4));
     HIP_TRY(ensure(S->ranges, sizeof(uint32_t) * 2 * n_keys));
+    if (cfg->schedule) HIP_TRY(ensure(S->sched, sizeof(uint32_t) * (n_keys + 1)));
     if (need_state) {
         HIP_TRY(ensure(S->T_final, sizeof(float) * npx));
         HIP_TRY(ensure(S->n_contrib, sizeof(uint32_t) * npx));
@@ -521,7 +576,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     HIP_TRY(ensure(S->scratch, std::max(scratch, sort_scratch_bytes(capacity))));
     {
         StageTimer tm(ctx, FDGS_STAGE_DUPLICATE, stream);
-        HIP_TRY(launch_duplicate(ov, S->offsets.as<uint64_t>(), S->rect.as<int32_t>(), view_of, counts + 0, n_max, rp,
+        HIP_TRY(launch_duplicate(ov, S->offsets.as<uint64_t>(), S->rect.as<int32_t>(), S->rec.as<Rec2D>(), view_of, counts + 0, n_max, rp,
                                  S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), counts + 1, capacity,
                                  ctx->overflow.as<int32_t>(), stream));
     }
@@ -551,7 +606,8 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
         HIP_TRY(launch_composite(rp, W, H, V, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
                                  S->rect.as<int32_t>(), out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
                                  acc ? acc + 3 : nullptr,
-                                 cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt, stream));
+                                 cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt,
+                                 cfg->schedule ? S->sched.as<uint32_t>() : nullptr, contrib, stream));
     }
     if (need_state && out_T)
         HIP_TRY(hipMemcpyAsync(out_T, S->T_final.p, sizeof(float) * npx, hipMemcpyDeviceToDevice, stream));
@@ -776,13 +832,14 @@ fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_sce
     HIP_TRY(ensure(ctx->tune_ref, img_bytes));
     HIP_TRY(ensure(ctx->tune_img, img_bytes));
     HIP_TRY(ensure(ctx->tune_diff, sizeof(unsigned long long)));
-    struct Cand { int tw, th, b, ppt; };
+    struct Cand { int tw, th, b, ppt, sched; };
     std::vector<Cand> cands;
     const int shapes[3][2] = {{16, 16}, {8, 8}, {32, 8}};
-    for (auto &sh : shapes)
-        for (int b : {64, 128, 256})
-            for (int ppt : {1, 2, 4})
-                if (sh[0] * sh[1] > 64 || ppt == 1) cands.push_back({sh[0], sh[1], b, ppt});
+    for (int sched : {1, 0})
+        for (auto &sh : shapes)
+            for (int b : {64, 128, 256})
+                for (int ppt : {1, 2, 4})
+                    if (sh[0] * sh[1] > 64 || ppt == 1) cands.push_back({sh[0], sh[1], b, ppt, sched});
     hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
     if (!e0 || !e1) return fail(FDGS_ERR_HIP, "%s: event creation failed", fn);
     double best = 1e300;
@@ -795,6 +852,7 @@ fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_sce
         c.tile_h = cands[i].th;
         c.batch = cands[i].b;
         c.pixels_per_thread = cands[i].ppt;
+        c.schedule = cands[i].sched;
         c.instance_capacity = 0;   // exact sizing: tile counts change with the tile shape
         float *dst = (i == 0 ? ctx->tune_ref : ctx->tune_img).as<float>();
         if (fdgs_status st = enqueue_batch(ctx, scenes, views, n_views, &c, per, true, dst, stream)) return st;
@@ -819,7 +877,8 @@ fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_sce
         }
         all_same = all_same && same;
         if (results && tried < max_results)
-            results[tried] = fdgs_tune_result{c.tile_w, c.tile_h, c.batch, c.pixels_per_thread, ms_best, same ? 1 : 0};
+            results[tried] = fdgs_tune_result{c.tile_w, c.tile_h, c.batch, c.pixels_per_thread, c.schedule, ms_best,
+                                              same ? 1 : 0};
         ++tried;
         if (same && ms_best < best) {
             best = ms_best;
@@ -834,6 +893,7 @@ fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_sce
         inout_cfg->tile_h = cands[best_i].th;
         inout_cfg->batch = cands[best_i].b;
         inout_cfg->pixels_per_thread = cands[best_i].ppt;
+        inout_cfg->schedule = cands[best_i].sched;
     }
     if (!all_same) return fail(FDGS_ERR_STATE, "%s: a configuration rendered different images", fn);
     return FDGS_OK;

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FDGS_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "k_preprocess.hip", "k_scan.hip", "k_sort.hip", "k_composite.hip", "k_backward.hip"]
-HEADERS = ["fdgs_internal.h", "dev_util.h", "dev_gauss.h", os.path.join("..", "..", "include", "fdgs.h")]
+HEADERS = ["fdgs_internal.h", "dev_util.h", "dev_gauss.h", "dev_cull.h", os.path.join("..", "..", "include", "fdgs.h")]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

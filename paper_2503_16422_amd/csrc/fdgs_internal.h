@@ -36,6 +36,8 @@ struct RenderParams {
     float bg[3];
     float alpha_min, alpha_max, t_min, dilation;
     int32_t temporal_cull;
+    int32_t tile_cull;      // list a record only in the tiles its ellipse reaches
+    double vanilla_level;   // cut level without opacity culling, incl. margin
 };
 
 // Launch wrappers (each .hip file owns its kernels).  All are asynchronous.
@@ -108,7 +110,7 @@ hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_
                                  const int64_t *n_vis_dev, int64_t n_max, int32_t *flag, hipStream_t s);
 // Tile key = view * tiles_per_view + ty * tiles_x + tx (view_of null: view 0).
 hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
-                            const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
+                            const Rec2D *rec, const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
                             const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,
                             const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, hipStream_t s);
 // dst[j] = src[idx[j]] for j < count.
@@ -126,12 +128,20 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
                                     int64_t capacity, uint64_t *acc, hipStream_t s);
 
 // Compositing.  pair_counter (optional) accumulates evaluated (pixel, Gaussian) pairs.
-// V views of W x H share one tile grid: block b renders tile b % n_tiles of
-// view b / n_tiles; view v writes out_rgb + v*3*W*H (out_T, n_contrib: + v*W*H).
+// V views of W x H share one tile grid: item i renders tile i % n_tiles of
+// view i / n_tiles; view v writes out_rgb + v*3*W*H (out_T, n_contrib: + v*W*H).
+// sched == NULL: one workgroup per item in item order.  Otherwise sched holds
+// V * n_tiles + 1 uint32 of scratch: the items are ordered longest list first
+// and taken by persistent workgroups.
+// contrib (optional): contrib[id] = 1 for every processed entry some pixel
+// blends (state and counters are then not recorded).
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
                             const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
-                            uint64_t *pair_counter, int32_t pixels_per_thread, hipStream_t s);
+                            uint64_t *pair_counter, int32_t pixels_per_thread, uint32_t *sched,
+                            uint8_t *contrib, hipStream_t s);
+// bits[w] bit j = (flags[32 w + j] != 0), j < 32, for n flags.
+hipError_t launch_flags_to_bits(const uint8_t *flags, int64_t n, uint32_t *bits, hipStream_t s);
 
 // Backward.
 hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,

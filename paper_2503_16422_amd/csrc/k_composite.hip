@@ -14,6 +14,8 @@
 // is exact to ~1e-6 px even at the right edge of a 1352-px image.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dev_util.h"
 #include "fdgs_internal.h"
 
@@ -58,21 +60,32 @@ struct CompArgs {
     unsigned long long *pairs;   // optional counter of evaluated pairs
     int32_t ppt;                 // pixels per thread (host-side dispatch only)
     int32_t V;                   // views sharing the launch
+    const uint32_t *order;       // persistent schedule: (view, tile) items, longest list first
+    uint32_t *work_counter;      // persistent schedule: next item to take (zeroed by the ordering kernel)
+    int32_t n_items;             // V x tiles per view
+    uint8_t *contrib;            // kMark: per processed entry, set to 1 when blended
 };
 
 // Thread layout: PPT consecutive pixels of one column per thread
 // (TW x TH / PPT threads); the column's dx terms and the LDS reads of a record
 // are shared by the thread's PPT pixels.
-template <int TW, int TH, int BATCH, int PPT, bool COUNT>
-__global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
+// What a compositor instance records beyond colour and transmittance.
+enum CompMode {
+    kPlain = 0,   // nothing
+    kState = 1,   // last contributor per pixel (for the adjoint)
+    kCount = 2,   // last contributor and the evaluated-pair count (profiling)
+    kMark = 3,    // flags every record some pixel blends (visibility masks)
+};
+
+// One (view, tile) item; s_rec is the workgroup's LDS staging array of
+// 3 x BATCH float4.  Every thread of the workgroup calls it.
+template <int TW, int TH, int BATCH, int PPT, int MODE>
+__device__ __forceinline__ void composite_item(const CompArgs &a, int item, float4 *s_rec) {
     constexpr int NT = TW * TH / PPT;
     static_assert(NT % 64 == 0, "whole wavefronts per tile");
-    __shared__ float4 s_g[BATCH];    // centre (block-relative), ka, kb
-    __shared__ float4 s_h[BATCH];    // kc, opacity, r, g
-    __shared__ float s_b[BATCH];     // b
     const int n_tiles = a.rp.tiles_x * a.rp.tiles_y;
-    const int view = blockIdx.x / n_tiles;
-    const int tile = blockIdx.x - view * n_tiles;
+    const int view = item / n_tiles;
+    const int tile = item - view * n_tiles;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
     const int lx = threadIdx.x % TW, ly0 = (threadIdx.x / TW) * PPT;
     const int px = tx * TW + lx, py0 = ty * TH + ly0;
@@ -82,11 +95,17 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
     const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;
     const float fx = (float)(px - bx0) + 0.5f;
     const float ox = (float)bx0, oy = (float)by0;
-    const uint32_t start = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
+    const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
     const float amin = a.rp.alpha_min, amax = a.rp.alpha_max, tmin = a.rp.t_min;
-    float fy[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    constexpr bool COUNT = MODE == kCount;
+    constexpr bool LAST = MODE == kState || MODE == kCount;
+    constexpr bool MARK = MODE == kMark;
+    constexpr float kInf = __builtin_huge_valf();
+    // thr[p]: the transmittance a blend must keep; t_min while the pixel is
+    // live, +inf once it has stopped (or lies outside the image), so a stopped
+    // pixel fails every later test and its T stays the T at the stop.
+    float fy[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], thr[PPT];
     uint32_t last[PPT], stop[PPT];
-    bool done[PPT];
     bool all_done = true;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -95,36 +114,42 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
         C0[p] = C1[p] = C2[p] = 0.0f;
         last[p] = 0;
         stop[p] = end - start;
-        done[p] = !(px < a.W && py0 + p < a.H);
-        all_done = all_done && done[p];
+        const bool inside = px < a.W && py0 + p < a.H;
+        thr[p] = inside ? tmin : kInf;
+        all_done = all_done && !inside;
     }
     for (uint32_t base = start; base < end; base += BATCH) {
+        if constexpr (PPT > 1) {
+            bool left = false;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) left = left || thr[p] < kInf;
+            all_done = !left;
+        }
         if (__syncthreads_count(!all_done) == 0) break;
         const int cnt = (int)min((uint32_t)BATCH, end - base);
         for (int k = threadIdx.x; k < cnt; k += NT) {
             const Rec2D r = a.rec[a.ids[base + k]];
             const float4 q = staged_conic(r);
-            s_g[k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
-            s_h[k] = make_float4(q.z, q.w, r.c.x, r.c.y);
-            s_b[k] = r.c.z;
+            s_rec[3 * k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
+            s_rec[3 * k + 1] = make_float4(q.z, q.w, r.c.x, r.c.y);
+            s_rec[3 * k + 2] = make_float4(r.c.z, __uint_as_float(a.ids[base + k]), 0.0f, 0.0f);
         }
         __syncthreads();
         if (!all_done) {
-            for (int k = 0; k < cnt; ++k) {
-                const float4 g = s_g[k];
-                const float4 h = s_h[k];
-                const float4 q = make_float4(g.z, g.w, h.x, h.y);
-                const float dx = fx - g.x;
-                const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
-                const uint32_t pos = base + k - start + 1;
-                if constexpr (PPT == 1) {
+            if constexpr (PPT == 1) {
+                for (int k = 0; k < cnt; ++k) {
+                    const float4 g = s_rec[3 * k];
+                    const float4 h = s_rec[3 * k + 1];
+                    const float4 q = make_float4(g.z, g.w, h.x, h.y);
+                    const float dx = fx - g.x;
+                    const uint32_t pos = base + k - start + 1;
                     // one pixel: branch, so a wavefront skips the blend when no lane takes it
-                    const float e = exp2_at(q, A, B, fy[0] - g.y);
+                    const float e = exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), fy[0] - g.y);
                     const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
                     if (alpha < amin) continue;
                     const float test = after(T[0], alpha);
-                    if (test < tmin) {
-                        done[0] = true;
+                    if (test < thr[0]) {
+                        thr[0] = kInf;
                         if constexpr (COUNT) stop[0] = pos;
                         all_done = true;
                         break;
@@ -132,31 +157,56 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
                     const float w = alpha * T[0];
                     C0[0] = fmaf(h.z, w, C0[0]);
                     C1[0] = fmaf(h.w, w, C1[0]);
-                    C2[0] = fmaf(s_b[k], w, C2[0]);
+                    C2[0] = fmaf(s_rec[3 * k + 2].x, w, C2[0]);
                     T[0] = test;
-                    last[0] = pos;
-                } else {
-                    // several pixels: predicated updates, no divergent branches per pixel
-                    const float cb = s_b[k];
+                    if constexpr (LAST) last[0] = pos;
+                    if constexpr (MARK) {
+                        // lanes here blended record k: the lowest one flags it
+                        if (lane_id() == __builtin_ctzll(__ballot(1)))
+                            a.contrib[__float_as_uint(s_rec[3 * k + 2].y)] = 1;
+                    }
+                }
+            } else {
+                // several pixels: select-based updates, no branches or lane masks per pixel;
+                // groups of 8 records, leaving the batch once all of the thread's pixels stopped
+                for (int k0 = 0; k0 < cnt; k0 += 8) {
+                    const int kn = min(cnt, k0 + 8);
+                    for (int k = k0; k < kn; ++k) {
+                        const float4 g = s_rec[3 * k];
+                        const float4 h = s_rec[3 * k + 1];
+                        const float4 q = make_float4(g.z, g.w, h.x, h.y);
+                        const float cb = s_rec[3 * k + 2].x;
+                        const float dx = fx - g.x;
+                        const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
+                        const uint32_t pos = base + k - start + 1;
+                        bool blended = false;
+#pragma unroll
+                        for (int p = 0; p < PPT; ++p) {
+                            // alpha below alpha_min enters as 0: the test then keeps T (>= t_min), w = 0
+                            const float e = exp2_at(q, A, B, fy[p] - g.y);
+                            const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
+                            const float al = alpha >= amin ? alpha : 0.0f;
+                            const float test = after(T[p], al);
+                            const bool ok = test >= thr[p];
+                            const float w = ok ? al * T[p] : 0.0f;
+                            C0[p] = fmaf(h.z, w, C0[p]);
+                            C1[p] = fmaf(h.w, w, C1[p]);
+                            C2[p] = fmaf(cb, w, C2[p]);
+                            if constexpr (LAST) last[p] = w > 0.0f ? pos : last[p];   // w >= alpha_min t_min > 0
+                            if constexpr (COUNT) stop[p] = (!ok && thr[p] < kInf) ? pos : stop[p];
+                            T[p] = ok ? test : T[p];
+                            thr[p] = ok ? thr[p] : kInf;
+                            if constexpr (MARK) blended = blended || w > 0.0f;
+                        }
+                        if constexpr (MARK) {
+                            const uint64_t m = __ballot(blended);
+                            if (m != 0ull && lane_id() == __builtin_ctzll(m))
+                                a.contrib[__float_as_uint(s_rec[3 * k + 2].y)] = 1;
+                        }
+                    }
                     bool left = false;
 #pragma unroll
-                    for (int p = 0; p < PPT; ++p) {
-                        const float e = exp2_at(q, A, B, fy[p] - g.y);
-                        const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
-                        const float test = after(T[p], alpha);
-                        const bool take = !done[p] && alpha >= amin;
-                        const bool stp = take && test < tmin;
-                        const bool use = take && !stp;
-                        const float w = use ? alpha * T[p] : 0.0f;
-                        C0[p] = fmaf(h.z, w, C0[p]);
-                        C1[p] = fmaf(h.w, w, C1[p]);
-                        C2[p] = fmaf(cb, w, C2[p]);
-                        T[p] = use ? test : T[p];
-                        last[p] = use ? pos : last[p];
-                        if constexpr (COUNT) stop[p] = stp ? pos : stop[p];
-                        done[p] = done[p] || stp;
-                        left = left || !done[p];
-                    }
+                    for (int p = 0; p < PPT; ++p) left = left || thr[p] < kInf;
                     if (!left) {
                         all_done = true;
                         break;
@@ -177,7 +227,9 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
             out_rgb[plane + pix] = C1[p] + T[p] * a.rp.bg[1];
             out_rgb[2 * plane + pix] = C2[p] + T[p] * a.rp.bg[2];
             if (a.out_T) a.out_T[view * plane + pix] = T[p];
-            if (a.n_contrib) a.n_contrib[view * plane + pix] = last[p];
+            if constexpr (LAST) {
+                if (a.n_contrib) a.n_contrib[view * plane + pix] = last[p];
+            }
             evaluated += stop[p];
         }
     }
@@ -185,6 +237,69 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
         const unsigned long long w = wave_sum((unsigned long long)evaluated);
         if (lane_id() == 0) atomicAdd(a.pairs, w);
     }
+}
+
+// Grid schedule: workgroup b renders item b (tiles in raster order, views in
+// turn).  Persistent schedule: a grid sized to the resident workgroups takes
+// items from a.order (longest tile list first, so the long lists do not start
+// last and leave the device idle at the end) through an atomic counter; every
+// workgroup leaves once the counter passes the item count.
+template <int TW, int TH, int BATCH, int PPT, int MODE, bool PERSIST>
+__global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
+    // per staged record three float4 at one address: centre (block-relative),
+    // ka, kb | kc, log2 opacity, r, g | b, -, -, -
+    __shared__ float4 s_rec[3 * BATCH];
+    if constexpr (!PERSIST) {
+        composite_item<TW, TH, BATCH, PPT, MODE>(a, blockIdx.x, s_rec);
+    } else {
+        __shared__ int s_item;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = (int)atomicAdd(a.work_counter, 1u);
+            __syncthreads();
+            const int it = s_item;
+            __syncthreads();   // s_item is rewritten only after every thread has read it
+            if (it >= a.n_items) break;
+            composite_item<TW, TH, BATCH, PPT, MODE>(a, (int)a.order[it], s_rec);
+        }
+    }
+}
+
+// Visibility flags (bytes) to LSB-first bit words: one ballot per wavefront.
+__global__ void __launch_bounds__(256) flags_to_bits_kernel(const uint8_t *flags, int64_t n, uint32_t *bits) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t m = __ballot(g < n && flags[g] != 0);
+    const int lane = lane_id();
+    const int64_t word = g >> 5;
+    if ((lane == 0 || lane == 32) && word < (n + 31) / 32)
+        bits[word] = lane == 0 ? (uint32_t)(m & 0xffffffffu) : (uint32_t)(m >> 32);
+}
+
+// Orders the V x tiles items by the bit length of their list length, longest
+// first (one workgroup; order inside a length class is arbitrary, which only
+// affects scheduling), and zeroes the persistent work counter.
+constexpr int kOrderNT = 1024;
+__global__ void __launch_bounds__(kOrderNT) tile_order_kernel(const uint32_t *ranges, int32_t n_items,
+                                                              uint32_t *order, uint32_t *work_counter) {
+    __shared__ uint32_t s_cnt[33];
+    if (threadIdx.x < 33) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    auto cls = [&](int i) {
+        const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
+        return len ? 32 - __clz(len) : 0;   // 0 (empty) .. 32
+    };
+    for (int i = threadIdx.x; i < n_items; i += kOrderNT) atomicAdd(&s_cnt[cls(i)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int c = 32; c >= 0; --c) {
+            const uint32_t k = s_cnt[c];
+            s_cnt[c] = run;
+            run += k;
+        }
+        *work_counter = 0u;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_items; i += kOrderNT) order[atomicAdd(&s_cnt[cls(i)], 1u)] = (uint32_t)i;
 }
 
 struct BwdArgs {
@@ -334,12 +449,40 @@ __global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
     }
 }
 
+// Workgroups of one kernel that fit on the device at once.
+template <typename K>
+int resident_groups(K kernel, int threads) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+template <int TW, int TH, int BATCH, int PPT, int MODE>
+void launch_fwd_sched(const CompArgs &a, int n_items, hipStream_t s) {
+    constexpr int NT = TW * TH / PPT;
+    if (a.order) {
+        auto k = composite_kernel<TW, TH, BATCH, PPT, MODE, true>;
+        static const int groups = resident_groups(k, NT);
+        const int grid = groups > 0 ? std::min(groups, n_items) : n_items;
+        hipLaunchKernelGGL(k, dim3(std::max(grid, 1)), dim3(NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT, MODE, false>), dim3(n_items), dim3(NT), 0, s, a);
+    }
+}
+
 template <int TW, int TH, int BATCH, int PPT>
 void launch_fwd_ppt(const CompArgs &a, int n_tiles, hipStream_t s) {
-    if (a.pairs)
-        hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT, true>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
+    if (a.contrib)
+        launch_fwd_sched<TW, TH, BATCH, PPT, kMark>(a, n_tiles, s);
+    else if (a.pairs)
+        launch_fwd_sched<TW, TH, BATCH, PPT, kCount>(a, n_tiles, s);
+    else if (a.n_contrib)
+        launch_fwd_sched<TW, TH, BATCH, PPT, kState>(a, n_tiles, s);
     else
-        hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT, false>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
+        launch_fwd_sched<TW, TH, BATCH, PPT, kPlain>(a, n_tiles, s);
 }
 
 // Pixels per thread: 1 for 8x8 tiles (one wavefront per tile), a.ppt (1, 2
@@ -390,12 +533,21 @@ void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
                             const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
-                            uint64_t *pair_counter, int32_t ppt, hipStream_t s) {
+                            uint64_t *pair_counter, int32_t ppt, uint32_t *sched, uint8_t *contrib,
+                            hipStream_t s) {
     if (ppt != 1 && ppt != 2 && ppt != 4) return hipErrorInvalidValue;
-    CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, n_contrib,
-               reinterpret_cast<unsigned long long *>(pair_counter), ppt, V};
     const int n_tiles = rp.tiles_x * rp.tiles_y * V;
+    CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, contrib ? nullptr : n_contrib,
+               contrib ? nullptr : reinterpret_cast<unsigned long long *>(pair_counter), ppt, V,
+               sched, sched ? sched + n_tiles : nullptr, n_tiles, contrib};
+    if (sched) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderNT), 0, s, ranges, n_tiles, sched,
+                                  sched + n_tiles);
     FDGS_DISPATCH(launch_fwd, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags_to_bits(const uint8_t *flags, int64_t n, uint32_t *bits, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(flags_to_bits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, flags, n, bits);
     return hipGetLastError();
 }
 

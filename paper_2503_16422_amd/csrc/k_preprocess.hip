@@ -12,7 +12,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "dev_cull.h"
 #include "dev_gauss.h"
+#include "dev_util.h"
 #include "fdgs_internal.h"
 
 namespace fdgs {
@@ -46,12 +48,14 @@ struct PreArgs {
     const int64_t *n_dev;      // device processed count (V == 1 only)
     int64_t n_total;           // processed entries over all views (upper bound when n_dev)
     RenderParams rp;
-    double vanilla_level;
     PreprocOut out;
 };
 
-// Processed entry j of view vd (local position i = j - vd.p_off).
-__device__ __forceinline__ void preprocess_one(const ViewDesc &vd, int64_t j, const PreArgs &a) {
+// Processed entry j of view vd (local position i = j - vd.p_off).  Returns
+// whether it is visible; then *rect4 and *ell describe its footprint for the
+// tile count.
+__device__ __forceinline__ bool preprocess_one(const ViewDesc &vd, int64_t j, const PreArgs &a, int4 *rect4,
+                                               CullEllipse *ell) {
     const int64_t i = j - vd.p_off;
     const int64_t g = vd.idx ? (int64_t)vd.idx[i] : i;
     Gauss4 G;
@@ -74,15 +78,11 @@ __device__ __forceinline__ void preprocess_one(const ViewDesc &vd, int64_t j, co
         if (a.rp.temporal_cull && opac < (double)a.rp.alpha_min) vis = false;
     }
     if (vis) {
-        const double q = cut_level(opac, (double)a.rp.alpha_min, a.rp.temporal_cull, a.vanilla_level);
+        const double q = cut_level(opac, (double)a.rp.alpha_min, a.rp.temporal_cull, a.rp.vanilla_level);
         r = pixel_rect(Pr, q, vd.cam.W, vd.cam.H);
         vis = r.x0 <= r.x1 && r.y0 <= r.y1;
     }
-    uint32_t tiles = 0;
     if (vis) {
-        const int tx0 = r.x0 / a.rp.tile_w, tx1 = r.x1 / a.rp.tile_w;
-        const int ty0 = r.y0 / a.rp.tile_h, ty1 = r.y1 / a.rp.tile_h;
-        tiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         const double det = Pr.c00 * Pr.c11 - Pr.c01 * Pr.c01;
         const double ca = Pr.c11 / det, cb = -Pr.c01 / det, cc = Pr.c00 / det;
         // view direction from the camera centre C = -R^T t to the conditional mean
@@ -102,27 +102,71 @@ __device__ __forceinline__ void preprocess_one(const ViewDesc &vd, int64_t j, co
         rec.c = make_float4(rgb[0], rgb[1], rgb[2], (float)Pr.z);
         a.out.rec[j] = rec;
         a.out.depth_key[j] = (uint64_t)__double_as_longlong(Pr.z);
-        reinterpret_cast<int4 *>(a.out.rect)[j] = make_int4(r.x0, r.y0, r.x1, r.y1);
+        const int4 r4 = make_int4(r.x0, r.y0, r.x1, r.y1);
+        reinterpret_cast<int4 *>(a.out.rect)[j] = r4;
+        *rect4 = r4;
+        *ell = cull_ellipse(rec, a.rp);
     }
-    a.out.tiles[j] = tiles;
     a.out.visible[j] = vis ? 1 : 0;
+    return vis;
 }
 
+// One thread per processed entry; then the workgroup counts its entries'
+// tiles row-parallel: the tile rows of the visible entries' rectangles are
+// enumerated (block scan of rows per entry) and spread over the threads, each
+// evaluating one row's tile columns (the evaluation tile-key emission
+// repeats), so a footprint spanning many rows does not hold up a wavefront.
 __global__ void __launch_bounds__(kBlock) preprocess_kernel(PreArgs a) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ int4 s_rect[kBlock];
+    __shared__ CullEllipse s_ell[kBlock];
+    __shared__ uint32_t s_rbase[kBlock], s_cnt[kBlock];
+    __shared__ uint32_t s_tmp[kBlock / 64 + 1];
+    const int t = threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * kBlock + t;
     const int64_t P = (a.V == 1 && a.n_dev) ? min(*a.n_dev, a.n_total) : a.n_total;
-    if (j >= P) return;
-    if (a.V == 1) {
-        preprocess_one(a.one, j, a);
-        return;
+    bool vis = false;
+    int4 r4 = make_int4(0, 0, -1, -1);
+    CullEllipse ell = {};
+    if (j < P) {
+        if (a.V == 1) {
+            vis = preprocess_one(a.one, j, a, &r4, &ell);
+        } else {
+            int lo = 0, hi = a.V - 1;         // last view whose range starts at or before j
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.table[mid].p_off <= j) lo = mid; else hi = mid - 1;
+            }
+            a.out.view_of[j] = (uint32_t)lo;
+            vis = preprocess_one(a.table[lo], j, a, &r4, &ell);
+        }
     }
-    int lo = 0, hi = a.V - 1;             // last view whose range starts at or before j
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.table[mid].p_off <= j) lo = mid; else hi = mid - 1;
+    const int tw = a.rp.tile_w, th = a.rp.tile_h;
+    uint32_t rows = 0, direct = 0;
+    if (vis) {
+        if (ell.a > 0.0f) rows = (uint32_t)(r4.w / th - r4.y / th + 1);
+        else direct = count_tiles(ell, r4, tw, th);   // whole rectangle, closed form
     }
-    a.out.view_of[j] = (uint32_t)lo;
-    preprocess_one(a.table[lo], j, a);
+    s_rect[t] = r4;
+    s_ell[t] = ell;
+    s_cnt[t] = direct;
+    uint32_t n_rows;
+    s_rbase[t] = block_exclusive_sum<kBlock>(rows, s_tmp, &n_rows);   // contains barriers
+    for (uint32_t row0 = 0; row0 < n_rows; row0 += kBlock) {
+        const uint32_t rho = row0 + (uint32_t)t;
+        if (rho < n_rows) {
+            int lo = 0, hi = kBlock - 1;      // last entry whose rows start at or before rho
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_rbase[mid] <= rho) lo = mid; else hi = mid - 1;
+            }
+            const int4 rr = s_rect[lo];
+            const int ty = rr.y / th + (int)(rho - s_rbase[lo]);
+            int c0, c1;
+            if (tile_row_span(s_ell[lo], rr, ty, tw, th, &c0, &c1)) atomicAdd(&s_cnt[lo], (uint32_t)(c1 - c0 + 1));
+        }
+    }
+    __syncthreads();
+    if (j < P) a.out.tiles[j] = s_cnt[t];
 }
 
 struct MaskKArgs {
@@ -186,7 +230,6 @@ hipError_t launch_preprocess(const ViewDesc *one, const ViewDesc *table, int32_t
     a.n_dev = n_dev;
     a.n_total = n_total;
     a.rp = rp;
-    a.vanilla_level = 2.0 * log(1.0 / (double)rp.alpha_min) * (1.0 + 1e-4) + 1e-4;
     a.out = out;
     const unsigned grid = (unsigned)((n_total + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kBlock), 0, s, a);

@@ -15,6 +15,7 @@
 // (tile, depth) keys over every instance.
 #include <hip/hip_runtime.h>
 
+#include "dev_cull.h"
 #include "dev_util.h"
 #include "fdgs_internal.h"
 
@@ -207,25 +208,36 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
     }
 }
 
-// Tile-key emission, load-balanced over instances.  Block b owns the visible
-// Gaussians at sorted positions [256 b, 256 b + 256) and therefore the
-// instances [off[256 b], off[256 b + 256]).  Its threads walk those instances
-// with a stride of 256 (coalesced writes); each finds its Gaussian by a
-// binary search over the block's offsets in LDS and its tile from the
-// position inside the Gaussian's tile rectangle (row-major), so a Gaussian
-// covering thousands of tiles is spread over the whole block.
+// Tile-key emission.  Block b owns the visible Gaussians at sorted positions
+// [256 b, 256 b + 256) and therefore the instances [off[256 b],
+// off[256 b + 256]).  Their tile rows (every row of each rectangle, Gaussian
+// by Gaussian) are processed 256 at a time: a thread finds its row's Gaussian
+// by a binary search over the rows' prefix in LDS and evaluates the row's
+// tile columns (the evaluation the per-Gaussian count used); a block scan of
+// the row counts places the rows' instances, which are contiguous.  The
+// block then writes those instances with consecutive threads (runs of
+// kDupRun, one binary search over the rows per run), so the stores are
+// coalesced however the rows' lengths vary.  Counts and emission use the same
+// float arithmetic, so each Gaussian fills exactly its slots; tile
+// coordinates are clamped into the rectangle and writes into [first, last),
+// so keys, ids and addresses stay in range whatever the counts hold.
 constexpr int kDupNT = 256;
 constexpr int kDupRun = 8;
 
 __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order, const uint64_t *offsets,
-                                                           const int32_t *rect, const uint32_t *view_of,
-                                                           const int64_t *n_vis_dev, int64_t n_max, RenderParams rp,
-                                                           uint32_t *tile_keys, uint32_t *ids,
-                                                           const int64_t *n_inst_dev, int64_t capacity,
-                                                           int32_t *overflow) {
-    __shared__ uint64_t s_off[kDupNT + 1];
-    __shared__ int32_t s_tx0[kDupNT], s_ty0[kDupNT], s_w[kDupNT];
+                                                           const int32_t *rect, const Rec2D *rec,
+                                                           const uint32_t *view_of, const int64_t *n_vis_dev,
+                                                           int64_t n_max, RenderParams rp, uint32_t *tile_keys,
+                                                           uint32_t *ids, const int64_t *n_inst_dev,
+                                                           int64_t capacity, int32_t *overflow) {
+    __shared__ int4 s_rect[kDupNT];
+    __shared__ CullEllipse s_ell[kDupNT];
     __shared__ uint32_t s_id[kDupNT], s_base[kDupNT];
+    __shared__ uint32_t s_rbase[kDupNT + 1];     // first row of each Gaussian in the block's row list
+    __shared__ uint32_t s_rpos[kDupNT + 1];      // per row of the chunk: first instance (block-relative)
+    __shared__ uint32_t s_rkey[kDupNT];          // per row: key of its first tile
+    __shared__ uint16_t s_rg[kDupNT];            // per row: Gaussian (block-local)
+    __shared__ uint32_t s_tmp[kDupNT / 64 + 1];
     const int64_t n_vis = count_of(n_vis_dev, n_max);
     const int64_t n_inst = *n_inst_dev;
     const int64_t j0 = (int64_t)blockIdx.x * kDupNT;
@@ -233,48 +245,78 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_inst > capacity) atomicOr(overflow, 1);
     const int cnt = (int)min((int64_t)kDupNT, n_vis - j0);
     const int t = threadIdx.x;
+    uint32_t nrows = 0;
     if (t < cnt) {
         const uint32_t id = order[j0 + t];
         const int4 r = reinterpret_cast<const int4 *>(rect)[id];
-        const int tx0 = r.x / rp.tile_w, tx1 = r.z / rp.tile_w;
-        s_tx0[t] = tx0;
-        s_ty0[t] = r.y / rp.tile_h;
-        s_w[t] = tx1 - tx0 + 1;
+        s_rect[t] = r;
+        s_ell[t] = cull_ellipse(rec[id], rp);
         s_id[t] = id;
         // tile keys of view v start at v * tiles per view
         s_base[t] = view_of ? view_of[id] * (uint32_t)(rp.tiles_x * rp.tiles_y) : 0u;
-        s_off[t] = offsets[j0 + t];
+        nrows = (uint32_t)(r.w / rp.tile_h - r.y / rp.tile_h + 1);
     }
-    if (t == 0) s_off[cnt] = (j0 + cnt < n_vis) ? offsets[j0 + cnt] : (uint64_t)n_inst;
+    uint32_t n_rows_total;
+    s_rbase[t] = block_exclusive_sum<kDupNT>(nrows, s_tmp, &n_rows_total);
+    if (t == 0) s_rbase[kDupNT] = n_rows_total;
+    const uint64_t first = offsets[j0];
+    const uint64_t end_g = (j0 + cnt < n_vis) ? offsets[j0 + cnt] : (uint64_t)n_inst;
+    const uint64_t last = min(end_g, (uint64_t)capacity);
     __syncthreads();
-    const uint64_t first = s_off[0];
-    const uint64_t last = min(s_off[cnt], (uint64_t)capacity);
-    // each thread writes kDupRun consecutive instances: one search per run
-    for (uint64_t e0 = first + (uint64_t)t * kDupRun; e0 < last; e0 += (uint64_t)kDupNT * kDupRun) {
-        int lo = 0, hi = cnt - 1;                      // largest i with s_off[i] <= e0
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= e0) lo = mid; else hi = mid - 1;
-        }
-        int w = s_w[lo];
-        const uint32_t k = (uint32_t)(e0 - s_off[lo]);
-        int ry = (int)(k / (uint32_t)w);
-        int rx = (int)k - ry * w;
-        const uint64_t e1 = min(e0 + kDupRun, last);
-        for (uint64_t e = e0; e < e1; ++e) {
-            if (e == s_off[lo + 1]) {                  // next Gaussian starts here
-                ++lo;
-                w = s_w[lo];
-                rx = 0;
-                ry = 0;
+    uint64_t carry = first;
+    for (uint32_t row0 = 0; row0 < n_rows_total; row0 += kDupNT) {
+        const uint32_t rho = row0 + (uint32_t)t;
+        uint32_t n = 0, key0 = 0;
+        int g = 0;
+        if (rho < n_rows_total) {
+            int lo = 0, hi = cnt - 1;                  // largest g with s_rbase[g] <= rho
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_rbase[mid] <= rho) lo = mid; else hi = mid - 1;
             }
-            tile_keys[e] = s_base[lo] + (uint32_t)((s_ty0[lo] + ry) * rp.tiles_x + s_tx0[lo] + rx);
-            ids[e] = s_id[lo];
-            if (++rx == w) {
-                rx = 0;
-                ++ry;
+            g = lo;
+            const int4 r = s_rect[g];
+            const int ty = r.y / rp.tile_h + (int)(rho - s_rbase[g]);
+            int c0, c1;
+            if (tile_row_span(s_ell[g], r, ty, rp.tile_w, rp.tile_h, &c0, &c1)) {
+                n = (uint32_t)(c1 - c0 + 1);
+                key0 = s_base[g] + (uint32_t)(ty * rp.tiles_x + c0);
             }
         }
+        uint32_t chunk_total;
+        const uint32_t pos = block_exclusive_sum<kDupNT>(n, s_tmp, &chunk_total);
+        s_rpos[t] = pos;
+        s_rkey[t] = key0;
+        s_rg[t] = (uint16_t)g;
+        if (t == 0) s_rpos[kDupNT] = chunk_total;
+        __syncthreads();
+        // instances [carry, carry + chunk_total): run e0 starts in the last row whose first instance is <= e0
+        const uint64_t stop = min(carry + chunk_total, last);
+        for (uint64_t e0 = carry + (uint64_t)t * kDupRun; e0 < stop; e0 += (uint64_t)kDupNT * kDupRun) {
+            const uint32_t k0 = (uint32_t)(e0 - carry);
+            int lo = 0, hi = kDupNT - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_rpos[mid] <= k0) lo = mid; else hi = mid - 1;
+            }
+            const uint64_t e1 = min(e0 + kDupRun, stop);
+            for (uint64_t e = e0; e < e1; ++e) {
+                const uint32_t k = (uint32_t)(e - carry);
+                while (k >= s_rpos[lo + 1]) ++lo;     // s_rpos[kDupNT] = chunk_total > k ends this
+                const int gg = s_rg[lo];
+                const int4 r = s_rect[gg];
+                // clamp the tile into the Gaussian's rectangle (a no-op when counts agree)
+                const uint32_t base = s_base[gg];
+                const uint32_t key = s_rkey[lo] + (k - s_rpos[lo]);
+                const int tile = (int)(key - base);
+                const int ty = min(max(tile / rp.tiles_x, r.y / rp.tile_h), r.w / rp.tile_h);
+                const int tx = min(max(tile - (tile / rp.tiles_x) * rp.tiles_x, r.x / rp.tile_w), r.z / rp.tile_w);
+                tile_keys[e] = base + (uint32_t)(ty * rp.tiles_x + tx);
+                ids[e] = s_id[gg];
+            }
+        }
+        carry += chunk_total;
+        __syncthreads();
     }
 }
 
@@ -394,12 +436,12 @@ hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_
 }
 
 hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
-                            const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
+                            const Rec2D *rec, const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
                             const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,
                             const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, hipStream_t s) {
     if (n_max == 0) return hipSuccess;
     hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_for(n_max, kDupNT)), dim3(kDupNT), 0, s, order, offsets,
-                       rect, view_of, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
+                       rect, rec, view_of, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
     return hipGetLastError();
 }
 

@@ -55,3 +55,35 @@ def need_gpu():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+
+
+def check_culled_binning(b, pre, st, W, H, tile_w, tile_h):
+    """Tile lists of a forward with tile culling, against the oracle's binning.
+
+    Each tile's list must be the oracle's rectangle list (depth order) with
+    some Gaussians left out, and must keep every Gaussian whose cut-level
+    ellipse holds a pixel centre of the tile.  Returns (GPU instances,
+    rectangle instances, reached pairs)."""
+    from oracle import binning as obin
+    n = pre.rect.shape[0]
+    ids_a, tiles_a, _ = obin.bin_gaussians(pre.rect, pre.depth, pre.visible, W, H, tile_w, tile_h)
+    key_a = tiles_a.astype(np.int64) * n + ids_a.astype(np.int64)      # rectangle lists, in list order
+    ranges = b["tile_ranges"].cpu().numpy().astype(np.int64)
+    ids_g = b["sorted_ids"].cpu().numpy().astype(np.int64)
+    tile_g = np.zeros(ids_g.size, dtype=np.int64)
+    for t in np.flatnonzero(ranges[:, 1] > ranges[:, 0]):
+        tile_g[ranges[t, 0]:ranges[t, 1]] = t
+    assert np.all(np.diff(ranges[:, 0]) >= 0) and ranges[-1, 1] <= ids_g.size
+    key_g = tile_g * n + ids_g
+    # positions of the GPU pairs in the rectangle lists: present and increasing
+    order = np.argsort(key_a, kind="stable")
+    at = np.searchsorted(key_a[order], key_g)
+    at = np.minimum(at, key_a.size - 1)
+    assert np.all(key_a[order][at] == key_g), "a listed pair outside the Gaussian's rectangle"
+    pos = order[at]
+    assert np.all(np.diff(pos) > 0), "a tile list is out of depth order"
+    q = oc.cut_level(pre.opac, st)
+    need = obin.reached_pairs(pre.rect, pre.uv, pre.conic, q, pre.visible, W, tile_w, tile_h)
+    missing = np.setdiff1d(need, key_g)
+    assert missing.size == 0, f"{missing.size} reached (tile, Gaussian) pairs dropped, first {missing[:4]}"
+    return ids_g.size, ids_a.size, need.size

@@ -36,7 +36,7 @@ def test_version_and_defaults(lib):
     assert b"gfx950" in lib.fdgs_version()
     cfg = _lib.default_cfg()
     assert (cfg.tile_w, cfg.tile_h, cfg.batch) == (16, 16, 128)
-    assert abs(cfg.alpha_min - 1 / 255) < 1e-8 and cfg.temporal_cull == 1
+    assert abs(cfg.alpha_min - 1 / 255) < 1e-8 and cfg.temporal_cull == 1 and cfg.tile_cull == 1 and cfg.schedule == 0
 
 
 def test_null_context_rejected_without_gpu(lib):
@@ -61,5 +61,38 @@ def test_struct_layouts_match_header():
     # sizes follow the C layout rules for the declared members
     assert ctypes.sizeof(_lib.Model) == 6 * 8 + 8 + 8
     assert ctypes.sizeof(_lib.Camera) == 9 * 8 + 3 * 8 + 5 * 8 + 2 * 4
-    assert ctypes.sizeof(_lib.RenderCfg) == 4 * 4 + 3 * 4 + 4 * 4 + 4 + 8
+    assert ctypes.sizeof(_lib.RenderCfg) == 4 * 4 + 3 * 4 + 4 * 4 + 4 + 4 + 4 + 8
     assert ctypes.sizeof(_lib.Grads) == 6 * 8
+
+
+C_NAMES = {"Model": "fdgs_model", "Camera": "fdgs_camera", "RenderCfg": "fdgs_render_cfg",
+           "MaskSpec": "fdgs_mask_spec", "Grads": "fdgs_grads", "Binning": "fdgs_binning", "View": "fdgs_view",
+           "TuneResult": "fdgs_tune_result", "Profile": "fdgs_profile"}
+
+
+def test_struct_offsets_match_c_compiler(tmp_path):
+    """Every ctypes mirror has the size and member offsets the C compiler
+    gives the header's struct."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("needs gcc and the ROCm headers")
+    lines = ['#include "fdgs.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    expect = []
+    for py, c in C_NAMES.items():
+        cls = getattr(_lib, py)
+        lines.append(f'printf("%zu\\n", sizeof({c}));')
+        expect.append(ctypes.sizeof(cls))
+        for name, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({c}, {name}));')
+            expect.append(getattr(cls, name).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", inc, str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect

@@ -8,7 +8,7 @@ from oracle import composite as oc
 from oracle import mask as omask
 from oracle import slicing as osl
 from paper_2503_16422_amd import _lib, inputs
-from tests.gpu_helpers import compare_image, oracle_settings
+from tests.gpu_helpers import check_culled_binning, compare_image, oracle_settings
 
 pytestmark = pytest.mark.gpu
 
@@ -127,9 +127,10 @@ def test_degenerate_gaussians_are_culled(ctx):
 @pytest.mark.parametrize("cull", [1, 0])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
 def test_binning_bit_exact(ctx, cull, tile):
+    """Without tile culling the lists are exactly the rectangle binning."""
     sc = inputs.tiny_scene(10_000, seed=0)
     cam = inputs.look_at_camera(0.0, 3.0, 256, 256)
-    cfg = _lib.default_cfg(temporal_cull=cull, tile_w=tile[0], tile_h=tile[1])
+    cfg = _lib.default_cfg(temporal_cull=cull, tile_w=tile[0], tile_h=tile[1], tile_cull=0)
     rgb, _, st = ctx.render(to_dev(sc), cam, 0.5, cfg, keep_state=True)
     b = ctx.binning(st)
     torch.cuda.synchronize()
@@ -149,6 +150,32 @@ def test_binning_bit_exact(ctx, cull, tile):
     ctx.release(st)
 
 
+@pytest.mark.parametrize("cull", [1, 0])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_culled_binning_between_reached_and_rectangle(ctx, cull, tile):
+    """With tile culling each list is the rectangle list minus Gaussians
+    whose ellipse misses the tile, in the same order, and the image is the
+    unculled one bit for bit."""
+    sc = inputs.tiny_scene(10_000, seed=0)
+    sc.log_scale[0] += 1.5                 # elongated footprints: most of a rectangle is missed
+    cam = inputs.look_at_camera(0.0, 3.0, 256, 256)
+    cfg = _lib.default_cfg(temporal_cull=cull, tile_w=tile[0], tile_h=tile[1])
+    model = to_dev(sc)
+    rgb, _, st = ctx.render(model, cam, 0.5, cfg, keep_state=True)
+    b = ctx.binning(st)
+    torch.cuda.synchronize()
+    ost = oracle_settings(cfg)
+    pre = oc.prepare(sc.arrays(), cam, 0.5, ost)
+    n_gpu, n_rect, n_need = check_culled_binning(b, pre, ost, 256, 256, *tile)
+    assert n_gpu <= 1.02 * n_need + 16, (n_gpu, n_need)
+    assert n_gpu < 0.95 * n_rect, (n_gpu, n_rect)
+    ctx.release(st)
+    cfg0 = _lib.default_cfg(temporal_cull=cull, tile_w=tile[0], tile_h=tile[1], tile_cull=0)
+    rgb0, _, _ = ctx.render(model, cam, 0.5, cfg0)
+    assert torch.equal(rgb, rgb0)
+    compare_image(rgb.cpu().numpy(), oc.composite(pre, cam, ost, mode="rect"))
+
+
 def test_depth_ties_ordered_by_position(ctx):
     # several Gaussians share an exact depth (same mean); order must follow index
     sc = inputs.tiny_scene(300, seed=3)
@@ -158,7 +185,8 @@ def test_depth_ties_ordered_by_position(ctx):
     sc.q_left[:, 100:140] = sc.q_left[:, 100:101]
     sc.q_right[:, 100:140] = sc.q_right[:, 100:101]
     cam = inputs.look_at_camera(0.0, 3.0, 64, 64)
-    rgb, _, st = ctx.render(to_dev(sc), cam, float(sc.mean[3, 100]), keep_state=True)
+    rgb, _, st = ctx.render(to_dev(sc), cam, float(sc.mean[3, 100]), _lib.default_cfg(tile_cull=0),
+                            keep_state=True)
     b = ctx.binning(st)
     torch.cuda.synchronize()
     pre = oc.prepare(sc.arrays(), cam, float(sc.mean[3, 100]), oracle_settings())
@@ -187,15 +215,15 @@ def test_tile_and_batch_configs_give_identical_images(ctx):
     for tile in ((16, 16), (8, 8), (32, 8)):
         for batch in (64, 128, 256):
             for cull in (1, 0):
-                for ppt in (1, 2, 4):
+                for ppt, tcull, sched in ((1, 1, 1), (2, 1, 0), (4, 1, 1), (2, 0, 1), (1, 0, 0)):
                     cfg = _lib.default_cfg(tile_w=tile[0], tile_h=tile[1], batch=batch, temporal_cull=cull,
-                                           pixels_per_thread=ppt)
+                                           pixels_per_thread=ppt, tile_cull=tcull, schedule=sched)
                     rgb, _, _ = ctx.render(model, cam, 0.5, cfg)
                     if base is None:
                         base = rgb.clone()
                     else:
                         diff = (rgb - base).abs()
-                        assert torch.equal(rgb, base), (tile, batch, cull, ppt, int((diff > 0).sum()),
+                        assert torch.equal(rgb, base), (tile, batch, cull, ppt, tcull, sched, int((diff > 0).sum()),
                                                         float(diff.max()))
 
 
@@ -288,3 +316,69 @@ def test_full_resolution_masked_frame_sampled(ctx):
     ref = oc.render(sc.arrays(), cam, float(frames[f]), st, idx=sel, mode="rect", pixels=(px, py))
     worst, nflag = compare_image(rgb.cpu().numpy(), ref, pixels=(px, py))
     print(f"1352x1014 masked frame: {n}/{sc.n} kept, max err {worst:.2e}, flagged {nflag}")
+
+
+@pytest.mark.parametrize("dilation", [0.3, 0.0])
+def test_tile_cull_keeps_images_on_anisotropic_scenes(ctx, dilation):
+    """Elongated, rotated footprints up to and past the condition number at
+    which culling falls back to the rectangle: the image with culling is the
+    image without it, bit for bit."""
+    cam = inputs.look_at_camera(10.0, 3.0, 300, 220)
+    for k, stretch in enumerate((1.0, 3.0, 5.0, 7.0)):
+        sc = inputs.tiny_scene(6000, seed=20 + k)
+        sc.log_scale[k % 3] += stretch
+        sc.log_scale[(k + 1) % 3] -= 1.0
+        model = to_dev(sc)
+        for cull in (1, 0):
+            cfg1 = _lib.default_cfg(temporal_cull=cull, dilation=dilation)
+            cfg0 = _lib.default_cfg(temporal_cull=cull, dilation=dilation, tile_cull=0)
+            a, Ta, sa = ctx.render(model, cam, 0.5, cfg1, want_T=True, keep_state=True)
+            b, Tb, _ = ctx.render(model, cam, 0.5, cfg0, want_T=True)
+            n1 = ctx.binning(sa)["n_inst"]
+            ctx.release(sa)
+            assert torch.equal(a, b) and torch.equal(Ta, Tb), (stretch, cull)
+            print(f"stretch {stretch} cull {cull}: {n1} instances with tile culling")
+
+
+def test_tile_cull_keeps_full_resolution_frames(ctx):
+    """The benchmark's scene and cameras at 1352x1014: identical frames with
+    and without tile culling, and fewer instances."""
+    sc = inputs.long_scene(200_000, seed=0)
+    cams = inputs.arc_cameras(20, 4.0, 1352, 1014)
+    model = to_dev(sc)
+    for c, t in ((0, 0.1), (5, 0.5), (13, 0.77), (19, 0.95)):
+        a, _, sa = ctx.render(model, cams[c], t, keep_state=True)
+        b, _, sb = ctx.render(model, cams[c], t, _lib.default_cfg(tile_cull=0), keep_state=True)
+        na, nb = ctx.binning(sa)["n_inst"], ctx.binning(sb)["n_inst"]
+        ctx.release(sa)
+        ctx.release(sb)
+        assert torch.equal(a, b), (c, t)
+        assert na < nb
+        print(f"camera {c} t {t}: {na} instances with tile culling, {nb} without")
+
+
+def test_contributed_mask_matches_oracle_and_keeps_keyframe_images(ctx):
+    """Keyframe visibility (mode 2): the GPU set holds every Gaussian the
+    FP64 oracle surely sees blended and only ones it may see blended, and a
+    masked render of a mask view at a keyframe equals the dense render."""
+    sc = inputs.long_scene(30_000, seed=3)
+    views = inputs.arc_cameras(4, 4.0, 200, 150)
+    model = to_dev(sc)
+    t_lo, t_hi = 0.3, 0.333
+    bits, idx, count = ctx.build_active_mask(model, [], t_lo, t_hi, _lib.MASK_CONTRIBUTED, views)
+    torch.cuda.synchronize()
+    n = int(count.item())
+    got = np.zeros(sc.n, dtype=bool)
+    got[idx[:n].cpu().numpy().view(np.uint32)] = True
+    unpacked = ((bits.cpu().numpy().view(np.uint32)[:, None] >> np.arange(32, dtype=np.uint32)) & 1)
+    assert np.array_equal(unpacked.astype(bool).ravel()[:sc.n], got)
+    sure, maybe = omask.contributed_keep(sc.arrays(), views, (t_lo, t_hi), oracle_settings())
+    assert np.all(got[sure]), int((sure & ~got).sum())
+    assert np.all(maybe[got]), int((got & ~maybe).sum())
+    assert 0 < n < sc.n
+    for t in (t_lo, t_hi):
+        for cam in views[::3]:
+            dense, Td, _ = ctx.render(model, cam, t, want_T=True)
+            masked, Tm, _ = ctx.render(model, cam, t, idx=idx, n_idx=count, want_T=True)
+            assert torch.equal(dense, masked) and torch.equal(Td, Tm)
+    print(f"contributed mask: {n} of {sc.n} kept; oracle sure {int(sure.sum())}, maybe {int(maybe.sum())}")
