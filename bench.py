@@ -67,21 +67,25 @@ def stage_bytes(name, prof, frames, masked, pixels):
     return 0
 
 
-def source_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_sha(paths):
+    """sha256 (16 hex digits) of the concatenated files."""
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel):
     """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current source of that kernel."""
+    were taken on the current sources of that kernel."""
     p = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         d = json.load(f)
-    src = os.path.join(ROOT, "paper_2503_16422_amd", "csrc", d.get("source", ""))
-    if not os.path.exists(src) or source_sha(src) != d.get("source_sha"):
+    srcs = [os.path.join(ROOT, "paper_2503_16422_amd", "csrc", x) for x in d.get("sources", [])]
+    if not srcs or not all(os.path.exists(x) for x in srcs) or source_sha(srcs) != d.get("source_sha"):
         return None
     return d.get("bytes_per_launch")
 
@@ -141,6 +145,29 @@ def timed_fps(ctx, model, cams, frames, masks, frame_window, cfg, steps, warmup,
     dt = time.perf_counter() - t0
     ctx.check_overflow()
     return steps / dt, dt
+
+
+def profile_stages(ctx, model, cams, frames, masks, frame_window, cfg, steps, start, out, masked, pixels):
+    """Per-stage HIP-event times of `steps` frames (the kernels the timed loop
+    runs) and the algorithmic HBM rate of each stage."""
+    from paper_2503_16422_amd import _lib
+    ctx.profile(True)
+    run_frames(ctx, model, cams, frames, masks, frame_window, cfg, steps, start, out)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    stages = {}
+    for name in _lib.STAGES[:8]:
+        calls = prof["calls"][name]
+        if not calls:
+            continue
+        avg_ms = prof["ms"][name] / calls
+        nbytes = stage_bytes(name, prof, steps, masked, pixels)
+        entry = {"avg_ms": round(avg_ms, 5), "algorithmic_GBps": round(nbytes / calls / (avg_ms * 1e-3) / 1e9, 1)}
+        entry["hbm_frac"] = round(entry["algorithmic_GBps"] / HBM_PEAK_GBS, 4)
+        stages[name] = entry
+    per_frame = {"processed": prof["processed"] / steps, "visible": prof["visible"] / steps,
+                 "instances": prof["instances"] / steps}
+    return stages, per_frame
 
 
 def cpu_baseline(scene, jobs):
@@ -287,6 +314,10 @@ def main():
     ap.add_argument("--config", default=None,
                     help="tile_w,tile_h,batch,pixels_per_thread,schedule: skip the autotuner and use this "
                          "configuration")
+    ap.add_argument("--dense-vanilla-only", action="store_true",
+                    help="only a few dense 3M-Gaussian unfiltered frames (for profiler runs)")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="only the forward+backward loop (500k Gaussians, 4 views; for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -309,9 +340,21 @@ def main():
             b.copy_(a)
         sync()
         del a, b
+    if args.fwd_bwd_only:
+        ms_iter, views, fb_stages = fwd_bwd(ctx, args.steps, args.warmup)
+        log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter; stages {json.dumps(fb_stages)}")
+        return
     W, H = 1352, 1014
     cams = inputs.arc_cameras(20, 4.0, W, H)
     out = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+    if args.dense_vanilla_only:
+        dmodel = GaussianModel.from_scene(inputs.dense_scene(3_000_000, seed=0), "cuda:0")
+        frames = inputs.frame_times(300)
+        vanilla = _lib.default_cfg(temporal_cull=0, tile_cull=0)
+        d_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, None, vanilla, args.steps, args.warmup, out,
+                             start=2000)
+        log(f"[bench] dense vanilla {d_fps:.1f} frames/s")
+        return
 
     # ---- headline: masked 200k scene -------------------------------------------------
     log("[bench] masked scene: generating 200k Gaussians")
@@ -344,10 +387,14 @@ def main():
     fps, dt = timed_fps(ctx, model, cams, frames, masks, frame_window, cfg, K, Wu, out)
     log(f"[bench] masked: {fps:.1f} frames/s ({dt * 1e3 / K:.3f} ms/frame); default config {fps_default:.1f}")
 
-    # same frames again with stage events
+    # same frames again with stage events (the kernels that ran timed), then
+    # once more with the compositor's pair-counting variant for the pair count
     ctx.profile(True)
     run_frames(ctx, model, cams, frames, masks, frame_window, cfg, K, Wu, out)
     prof = ctx.profile_read(reset=True)
+    ctx.profile(True, count_pairs=True)
+    run_frames(ctx, model, cams, frames, masks, frame_window, cfg, K, Wu, out)
+    prof["pairs"] = ctx.profile_read(reset=True)["pairs"]
     ctx.profile(False)
     stages = {}
     for name in _lib.STAGES[:8]:
@@ -366,7 +413,7 @@ def main():
     comp["achieved_TFLOPs"] = round(comp_tflops, 3)
     dominant = max(stages, key=lambda s: stages[s]["avg_ms"])
     if dominant == "composite":
-        kname = (f"composite_kernel<{cfg.tile_w},{cfg.tile_h},{cfg.batch},{cfg.pixels_per_thread},false,"
+        kname = (f"composite_kernel<{cfg.tile_w}, {cfg.tile_h}, {cfg.batch}, {cfg.pixels_per_thread}, 0, "
                  f"{'true' if cfg.schedule else 'false'}>")
         roof = {"bound": "alu", "kernel": kname, "achieved": round(comp_tflops, 3),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(comp_tflops / FP32_PEAK_TFLOPS, 4),
@@ -409,6 +456,9 @@ def main():
         n_dense = 16
         vanilla = _lib.default_cfg(temporal_cull=0, tile_cull=0)
         d_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, vanilla, n_dense, 3, out, start=2000)
+        d_stages, d_work = profile_stages(ctx, dmodel, cams, frames, None, frame_window, vanilla, n_dense, 2003,
+                                          out, False, W * H)
+        log(f"[bench] dense vanilla stages: {json.dumps(d_stages)}")
         dt_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, _lib.default_cfg(temporal_cull=0),
                               n_dense, 3, out, start=2000)
         dc_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, _lib.default_cfg(), n_dense, 3, out,
@@ -417,7 +467,9 @@ def main():
         dm_fps, _ = timed_fps(ctx, dmodel, cams, frames, dmasks, dfw, _lib.default_cfg(), 60, 5, out, start=2000)
         log(f"[bench] dense: vanilla {d_fps:.1f}, +tile cull {dt_fps:.1f}, +temporal cull {dc_fps:.1f}, "
             f"+mask {dm_fps:.1f} frames/s")
-        extra["dense_3M"] = {"vanilla_fps": round(d_fps, 2), "vanilla_tile_cull_fps": round(dt_fps, 2),
+        extra["dense_3M"] = {"vanilla_fps": round(d_fps, 2), "vanilla_stages": d_stages,
+                             "vanilla_per_frame": {k: int(v) for k, v in d_work.items()},
+                             "vanilla_tile_cull_fps": round(dt_fps, 2),
                              "temporal_cull_fps": round(dc_fps, 2),
                              "masked_fps": round(dm_fps, 2), "mask_build_ms_per_window": round(dmask_ms, 2),
                              "kept_mean": int(np.mean(dkept))}

@@ -341,7 +341,9 @@ typedef struct {
     uint64_t pairs;                  /* (pixel, Gaussian) evaluations      */
 } fdgs_profile;
 
-/* Turn profiling on (1) or off (0) for subsequent calls on this context. */
+/* Profiling for subsequent calls on this context: 0 off; 1 stage events and
+ * work counts (the compositor is the one that runs unprofiled); 2 as 1 plus
+ * the evaluated-pair count (a counting variant of the compositor). */
 FDGS_API fdgs_status fdgs_profile_enable(fdgs_ctx *ctx, int32_t enable);
 /* Read (and with reset=1 clear) the totals.  Synchronises the device. */
 FDGS_API fdgs_status fdgs_profile_read(fdgs_ctx *ctx, fdgs_profile *out, int32_t reset);

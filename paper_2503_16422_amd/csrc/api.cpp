@@ -107,6 +107,7 @@ struct fdgs_state {
     int64_t n_max = 0;
     int64_t capacity = 0;
     uint32_t *sorted_ids = nullptr;   // points into tids or tids2
+    uint32_t *vis_list = nullptr;     // visible positions in ascending order (vis_pos), for the adjoint
     uint32_t *sorted_keys = nullptr;
     int32_t W = 0, H = 0;
 
@@ -132,7 +133,7 @@ struct fdgs_ctx {
     Buf mask_flags, mask_img;      // contributed-mode visibility bytes and the keyframe image
     int64_t *host_counts = nullptr;  // pinned
     // profiling
-    bool prof = false;
+    int prof = 0;                  // 0 off, 1 stage events and counts, 2 also evaluated pairs
     Buf prof_acc;                  // uint64[4]: processed, visible, instances, pairs
     std::vector<hipEvent_t> free_events;
     std::vector<PendingStage> pending;
@@ -532,8 +533,10 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     }
     {
         StageTimer tm(ctx, FDGS_STAGE_COMPACT, stream);
+        if (need_state) HIP_TRY(ensure(S->vis_pos, sizeof(uint32_t) * n_max));
         HIP_TRY(compact_visible(S->visible.as<uint8_t>(), S->depth_key.as<uint64_t>(), n_dev, n_max, counts + 0,
-                                S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->scratch.p, stream));
+                                S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(),
+                                need_state ? S->vis_pos.as<uint32_t>() : nullptr, S->scratch.p, stream));
     }
     uint32_t *ov = nullptr;
     {
@@ -556,6 +559,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
             if (alt_v) ov = vv;
         }
     }
+    S->vis_list = need_state ? S->vis_pos.as<uint32_t>() : nullptr;
     {
         StageTimer tm(ctx, FDGS_STAGE_OFFSETS, stream);
         HIP_TRY(scan_u32_to_u64(S->tiles.as<uint32_t>(), ov, S->offsets.as<uint64_t>(), counts + 0, n_max,
@@ -605,7 +609,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
         StageTimer tm(ctx, FDGS_STAGE_COMPOSITE, stream);
         HIP_TRY(launch_composite(rp, W, H, V, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
                                  S->rect.as<int32_t>(), out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
-                                 acc ? acc + 3 : nullptr,
+                                 acc && ctx->prof == 2 ? acc + 3 : nullptr,
                                  cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt,
                                  cfg->schedule ? S->sched.as<uint32_t>() : nullptr, contrib, stream));
     }
@@ -923,7 +927,8 @@ fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *
         StageTimer tm(ctx, FDGS_STAGE_BWD_PREPROCESS, stream);
         const int64_t *n_proc_dev = S->idx ? S->n_idx_dev : nullptr;
         HIP_TRY(launch_preprocess_backward(kmodel(&S->model), S->idx, n_proc_dev, S->n_max, S->cam, S->t, S->rp,
-                                           S->visible.as<uint8_t>(), S->g2d.as<float>(), *grads, stream));
+                                           S->vis_list, S->counts.as<int64_t>(), S->g2d.as<float>(), *grads,
+                                           stream));
     }
     return FDGS_OK;
 }
@@ -973,7 +978,7 @@ fdgs_status fdgs_profile_enable(fdgs_ctx *ctx, int32_t enable) {
         HIP_TRY(ensure(ctx->prof_acc, 4 * sizeof(uint64_t)));
         HIP_TRY(hipMemset(ctx->prof_acc.p, 0, 4 * sizeof(uint64_t)));
     }
-    ctx->prof = enable != 0;
+    ctx->prof = enable <= 0 ? 0 : (enable >= 2 ? 2 : 1);
     return FDGS_OK;
 }
 

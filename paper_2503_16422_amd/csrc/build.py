@@ -20,17 +20,23 @@ BUILD = os.path.join(ROOT, "_build", "fdgs")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FDGS_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "k_preprocess.hip", "k_scan.hip", "k_sort.hip", "k_composite.hip", "k_backward.hip"]
-HEADERS = ["fdgs_internal.h", "dev_util.h", "dev_gauss.h", "dev_cull.h", os.path.join("..", "..", "include", "fdgs.h")]
+SOURCES = ["api.cpp", "k_preprocess.hip", "k_scan.hip", "k_sort.hip", "k_composite.hip", "k_composite_bwd.hip", "k_backward.hip"]
+HEADERS = ["fdgs_internal.h", "dev_util.h", "dev_gauss.h", "dev_cull.h", "dev_composite.h", os.path.join("..", "..", "include", "fdgs.h")]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]
 
 
+# Per-file flags.  The adjoint compositor adds each wavefront's reduced value
+# into LDS from one lane; LLVM's atomic optimizer would wrap every such add in
+# a lane loop (readlane / mbcnt / exec juggling), so it is off for that file.
+EXTRA = {"k_composite_bwd.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", os.path.join(HERE, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(src, []) + ["-c", os.path.join(HERE, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

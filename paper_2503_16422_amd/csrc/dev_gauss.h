@@ -248,9 +248,18 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float d
 
 // rgb = max(0, sum_k sh_k Y_k(d) + 0.5) per channel; raw[] gets the value
 // before the clamp.
-__device__ __forceinline__ void sh_to_rgb(const float *sh, int64_t n, int64_t g, int degree,
-                                          float dx, float dy, float dz, float rgb[3],
-                                          float raw[3] = nullptr) {
+// The (degree + 1)^2 x 3 SH coefficients of Gaussian g (coef[k * 3 + ch]);
+// the others are set to 0.  All loads are issued before any is used.
+__device__ __forceinline__ void load_sh(const float *sh, int64_t n, int64_t g, int degree, float coef[48]) {
+    const int nk = (degree + 1) * (degree + 1);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) coef[k * 3 + ch] = k < nk ? sh[((int64_t)(k * 3 + ch)) * n + g] : 0.0f;
+}
+
+__device__ __forceinline__ void sh_eval(const float coef[48], int degree, float dx, float dy, float dz,
+                                        float rgb[3], float raw[3] = nullptr) {
     float Y[16];
     sh_basis(dx, dy, dz, Y);
     const int nk = (degree + 1) * (degree + 1);
@@ -259,10 +268,18 @@ __device__ __forceinline__ void sh_to_rgb(const float *sh, int64_t n, int64_t g,
         float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            if (k < nk) acc += Y[k] * sh[((int64_t)(k * 3 + ch)) * n + g];
+            if (k < nk) acc += Y[k] * coef[k * 3 + ch];
         if (raw) raw[ch] = acc + 0.5f;
         rgb[ch] = fmaxf(acc + 0.5f, 0.0f);
     }
+}
+
+__device__ __forceinline__ void sh_to_rgb(const float *sh, int64_t n, int64_t g, int degree,
+                                          float dx, float dy, float dz, float rgb[3],
+                                          float raw[3] = nullptr) {
+    float coef[48];
+    load_sh(sh, n, g, degree, coef);
+    sh_eval(coef, degree, dx, dy, dz, rgb, raw);
 }
 
 }  // namespace fdgs

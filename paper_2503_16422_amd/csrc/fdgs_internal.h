@@ -88,9 +88,11 @@ hipError_t scan_flags_u8(const uint8_t *in, uint32_t *out, const int64_t *n_dev,
 hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t *out,
                            const int64_t *n_dev, int64_t n_max, int64_t *total,
                            void *scratch, hipStream_t s);
-// Visible entries in order -> keys32 = float32 bits of their depth, vals = position; *total = count.
+// Visible entries in order -> keys32 = float32 bits of their depth, vals = position (and, when asc is
+// not NULL, asc = position too: a copy the depth sort does not overwrite); *total = count.
 hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
-                           int64_t *total, uint32_t *keys32, uint32_t *vals, void *scratch, hipStream_t s);
+                           int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, void *scratch,
+                           hipStream_t s);
 hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t *count,
                         void *scratch, hipStream_t s);
 size_t compact_scratch_bytes(int64_t n);
@@ -151,7 +153,8 @@ hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t 
                                      hipStream_t s);
 hipError_t launch_preprocess_backward(const KModel &m, const uint32_t *idx, const int64_t *n_dev,
                                       int64_t n_max, const KCam &cam, double t,
-                                      const RenderParams &rp, const uint8_t *visible,
-                                      const float *g2d, const fdgs_grads &grads, hipStream_t s);
+                                      const RenderParams &rp, const uint32_t *vis_list,
+                                      const int64_t *n_vis_dev, const float *g2d, const fdgs_grads &grads,
+                                      hipStream_t s);
 
 }  // namespace fdgs

@@ -23,15 +23,21 @@ struct BArgs {
     KCam cam;
     double t;
     double dilation;
-    const uint8_t *visible;
+    const uint32_t *vis_list;   // processed positions of the visible Gaussians, ascending
+    const int64_t *n_vis_dev;   // their count (device)
     const float *g2d;
     fdgs_grads grads;
 };
 
+// One thread per visible Gaussian, through the forward's ascending list of
+// visible positions: no lane idles on a culled Gaussian, and neighbouring
+// threads read and update neighbouring entries of the parameter planes.
 __global__ void __launch_bounds__(kBlock) preprocess_bwd_kernel(BArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t P = a.n_dev ? min(*a.n_dev, a.n_max) : a.n_max;
-    if (i >= P || !a.visible[i]) return;
+    if (j >= min(*a.n_vis_dev, P)) return;
+    const int64_t i = a.vis_list[j];
+    if (i >= P) return;
     const int64_t n = a.m.n;
     const int64_t g = a.idx ? (int64_t)a.idx[i] : i;
     if (g >= n) return;
@@ -122,8 +128,9 @@ __global__ void __launch_bounds__(kBlock) preprocess_bwd_kernel(BArgs a) {
         vdir[k] = mean3[k] + (Rc[k] * a.cam.t[0] + Rc[3 + k] * a.cam.t[1] + Rc[6 + k] * a.cam.t[2]);
     const double vlen = sqrt(vdir[0] * vdir[0] + vdir[1] * vdir[1] + vdir[2] * vdir[2]);
     const double dirx = vdir[0] / vlen, diry = vdir[1] / vlen, dirz = vdir[2] / vlen;
-    float rgb[3], raw[3];
-    sh_to_rgb(a.m.sh, n, g, a.m.sh_degree, (float)dirx, (float)diry, (float)dirz, rgb, raw);
+    float coef[48], rgb[3], raw[3];
+    load_sh(a.m.sh, n, g, a.m.sh_degree, coef);
+    sh_eval(coef, a.m.sh_degree, (float)dirx, (float)diry, (float)dirz, rgb, raw);
     float Y[16], dYx[16], dYy[16], dYz[16];
     sh_basis((float)dirx, (float)diry, (float)dirz, Y);
     sh_basis_grad((float)dirx, (float)diry, (float)dirz, dYx, dYy, dYz);
@@ -133,12 +140,15 @@ __global__ void __launch_bounds__(kBlock) preprocess_bwd_kernel(BArgs a) {
     for (int ch = 0; ch < 3; ++ch) {
         const float draw = raw[ch] < 0.0f ? 0.0f : (float)drgb[ch];
         if (draw == 0.0f) continue;
+        // one channel's gradient plane entries: all loads first, then the stores
+        float gsh[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) gsh[k] = k < nk ? a.grads.sh[((int64_t)(k * 3 + ch)) * n + g] : 0.0f;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (k >= nk) continue;
-            const int64_t o = ((int64_t)(k * 3 + ch)) * n + g;
-            a.grads.sh[o] += Y[k] * draw;
-            const float c = a.m.sh[o] * draw;
+            a.grads.sh[((int64_t)(k * 3 + ch)) * n + g] = gsh[k] + Y[k] * draw;
+            const float c = coef[k * 3 + ch] * draw;
             ddir[0] += c * dYx[k];
             ddir[1] += c * dYy[k];
             ddir[2] += c * dYz[k];
@@ -292,24 +302,35 @@ __global__ void __launch_bounds__(kBlock) preprocess_bwd_kernel(BArgs a) {
     dqp[3] = -dRr[0][3] + dRr[1][2] - dRr[2][1] + dRr[3][0];
     const double pa = qa[0] * dqa[0] + qa[1] * dqa[1] + qa[2] * dqa[2] + qa[3] * dqa[3];
     const double pp = qp[0] * dqp[0] + qp[1] * dqp[1] + qp[2] * dqp[2] + qp[3] * dqp[3];
+    // all current values first, then the stores (the planes may alias as far as the compiler knows)
+    float gm[4], gl[4], gqa[4], gqp[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        a.grads.mean[k * n + g] += (float)dmu[k];
-        a.grads.log_scale[k * n + g] += (float)dls[k];
-        a.grads.q_left[k * n + g] += (float)((dqa[k] - qa[k] * pa) / nl);
-        a.grads.q_right[k * n + g] += (float)((dqp[k] - qp[k] * pp) / nr);
+        gm[k] = a.grads.mean[k * n + g];
+        gl[k] = a.grads.log_scale[k * n + g];
+        gqa[k] = a.grads.q_left[k * n + g];
+        gqp[k] = a.grads.q_right[k * n + g];
     }
-    a.grads.opacity_logit[g] += (float)dlogit;
+    const float go = a.grads.opacity_logit[g];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a.grads.mean[k * n + g] = gm[k] + (float)dmu[k];
+        a.grads.log_scale[k * n + g] = gl[k] + (float)dls[k];
+        a.grads.q_left[k * n + g] = gqa[k] + (float)((dqa[k] - qa[k] * pa) / nl);
+        a.grads.q_right[k * n + g] = gqp[k] + (float)((dqp[k] - qp[k] * pp) / nr);
+    }
+    a.grads.opacity_logit[g] = go + (float)dlogit;
 }
 
 }  // namespace
 
 hipError_t launch_preprocess_backward(const KModel &m, const uint32_t *idx, const int64_t *n_dev,
                                       int64_t n_max, const KCam &cam, double t,
-                                      const RenderParams &rp, const uint8_t *visible,
-                                      const float *g2d, const fdgs_grads &grads, hipStream_t s) {
+                                      const RenderParams &rp, const uint32_t *vis_list,
+                                      const int64_t *n_vis_dev, const float *g2d, const fdgs_grads &grads,
+                                      hipStream_t s) {
     if (n_max == 0) return hipSuccess;
-    BArgs a{m, idx, n_dev, n_max, cam, t, (double)rp.dilation, visible, g2d, grads};
+    BArgs a{m, idx, n_dev, n_max, cam, t, (double)rp.dilation, vis_list, n_vis_dev, g2d, grads};
     const unsigned grid = (unsigned)((n_max + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(preprocess_bwd_kernel, dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();

@@ -1,13 +1,13 @@
-// Per-tile front-to-back compositing (Eq. 2 with alpha from Eq. 3) and its
-// adjoint.
+// Per-tile front-to-back compositing (Eq. 2 with alpha from Eq. 3).
 //
-// One workgroup per screen tile, one pixel per thread.  The tile's depth-ordered
-// list is walked in batches: the workgroup stages a batch of records in LDS
-// (centre relative to the tile origin, pre-scaled conic, opacity, colour), then
-// every pixel evaluates the batch.  A pixel stops before the Gaussian that would
-// take its transmittance below t_min; the workgroup leaves the list as soon as
-// every pixel has stopped.  No MFMA: per (pixel, Gaussian) pair the work is an
-// exponential and a dozen FMAs, not a contraction.
+// One workgroup per screen tile; a thread owns 1, 2 or 4 pixels of a column.
+// The tile's depth-ordered list is walked in batches: the workgroup stages a
+// batch of records in LDS (centre relative to the tile origin, pre-scaled
+// conic, opacity, colour), then every pixel evaluates the batch.  A pixel
+// stops before the Gaussian that would take its transmittance below t_min;
+// the workgroup leaves the list as soon as every pixel has stopped.  No MFMA:
+// per (pixel, Gaussian) pair the work is an exponential and a dozen FMAs, not
+// a contraction.
 //
 // Precision: the centre is stored as a float pair (hi + lo) and re-centred on
 // the tile's 32x32 block while staging, so the per-pair offset dx = px + 0.5 - u
@@ -16,37 +16,14 @@
 
 #include <algorithm>
 
+#include "dev_composite.h"
 #include "dev_util.h"
 #include "fdgs_internal.h"
 
 namespace fdgs {
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.69314718055994531f;
-
-// Staged form of a record's conic and opacity: base-2 exponent coefficients
-// and log2(opacity), so that
-//   opacity * exp(-1/2 d^T conic d) = exp2(ka dx^2 + kb dx dy + kc dy^2 + lo).
-__device__ __forceinline__ float4 staged_conic(const Rec2D &r) {
-    return make_float4(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y, -0.5f * kLog2e * r.b.z, __log2f(r.b.w));
-}
-
-// Base-2 exponent of opacity x 2D Gaussian at offset (dx, dy):
-//   e = ((ka dx) dx + lo) + dy (kb dx + kc dy).
-// The dx-only terms are computed once per column when a thread owns several
-// pixels of one column; every kernel evaluates exactly this expression, so
-// forward, adjoint and all tile shapes take identical alpha decisions.
-__device__ __forceinline__ float exp2_col_a(float4 q, float dx) { return fmaf(q.x * dx, dx, q.w); }
-__device__ __forceinline__ float exp2_col_b(float4 q, float dx) { return q.y * dx; }
-__device__ __forceinline__ float exp2_at(float4 q, float A, float B, float dy) {
-    return fmaf(dy, fmaf(q.z, dy, B), A);
-}
-__device__ __forceinline__ float gauss_exp2(float4 q, float dx, float dy) {
-    return exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), dy);
-}
-// Transmittance after blending alpha in front of T.
-__device__ __forceinline__ float after(float T, float alpha) { return fmaf(-alpha, T, T); }
+using namespace comp;
 
 struct CompArgs {
     RenderParams rp;
@@ -302,153 +279,6 @@ __global__ void __launch_bounds__(kOrderNT) tile_order_kernel(const uint32_t *ra
     for (int i = threadIdx.x; i < n_items; i += kOrderNT) order[atomicAdd(&s_cnt[cls(i)], 1u)] = (uint32_t)i;
 }
 
-struct BwdArgs {
-    RenderParams rp;
-    int32_t W, H;
-    const uint32_t *ranges;
-    const uint32_t *ids;
-    const Rec2D *rec;
-    const float *T_final;
-    const uint32_t *n_contrib;
-    const float *dL;
-    float *g2d;        // [n_proc][9]: du, dv, d conic a, b, c, d opacity, d rgb
-};
-
-// Adjoint, walking each pixel's list back to front from its last contributor.
-// The transmittance in front of Gaussian i is recovered as T_{i+1} / (1 - a_i)
-// from the stored final T, so no per-pixel list is kept.  With g = dL/dC and
-// S the colour accumulated behind i (absolute weights):
-//   dL/dc_i = a_i T_i g
-//   dL/da_i = T_i c_i.g - (S.g + T_final bg.g) / (1 - a_i)
-// then a_i = min(a_max, o_i G_i) -> (o_i, conic, centre).  Per-Gaussian sums
-// are reduced across the wavefront before one atomic add per value.
-template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW *TH) composite_bwd_kernel(BwdArgs a) {
-    constexpr int NT = TW * TH;
-    __shared__ float2 s_xy[BATCH];
-    __shared__ float4 s_cn[BATCH];    // staged conic and opacity, as in the forward
-    __shared__ float4 s_rgb[BATCH];
-    __shared__ uint32_t s_id[BATCH];
-    __shared__ float s_io[BATCH];     // 1 / opacity
-    __shared__ float s_acc[BATCH * 9]; // per-Gaussian gradient sums of the tile
-    const int tile = blockIdx.x;
-    const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool inside = px < a.W && py < a.H;
-    const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;   // as in the forward
-    const float fx = (float)(px - bx0) + 0.5f, fy = (float)(py - by0) + 0.5f;
-    const float ox = (float)bx0, oy = (float)by0;
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const float amin = a.rp.alpha_min, amax = a.rp.alpha_max;
-    const int64_t pix = (int64_t)py * a.W + px;
-    const int64_t plane = (int64_t)a.W * a.H;
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f, T = 1.f;
-    uint32_t last = 0;
-    if (inside) {
-        g0 = a.dL[pix];
-        g1 = a.dL[plane + pix];
-        g2 = a.dL[2 * plane + pix];
-        T = a.T_final[pix];
-        last = a.n_contrib[pix];
-    }
-    const float bgdot = T * (a.rp.bg[0] * g0 + a.rp.bg[1] * g1 + a.rp.bg[2] * g2);   // T_final bg.g
-    float S0 = 0.f, S1 = 0.f, S2 = 0.f;
-    // block-wide maximum of `last` bounds the walk
-    __shared__ uint32_t s_max;
-    if (threadIdx.x == 0) s_max = 0;
-    __syncthreads();
-    atomicMax(&s_max, last);
-    __syncthreads();
-    const uint32_t walk_end = start + s_max;
-    const int lane = lane_id();
-    for (int j = threadIdx.x; j < BATCH * 9; j += NT) s_acc[j] = 0.0f;
-    for (int64_t top = (int64_t)walk_end; top > (int64_t)start; top -= BATCH) {
-        const uint32_t lo = (uint32_t)max((int64_t)start, top - BATCH);
-        const int cnt = (int)(top - lo);
-        __syncthreads();
-        for (int k = threadIdx.x; k < cnt; k += NT) {
-            const uint32_t id = a.ids[lo + k];
-            const Rec2D r = a.rec[id];
-            s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
-            s_cn[k] = staged_conic(r);
-            s_rgb[k] = r.c;
-            s_id[k] = id;
-            s_io[k] = 1.0f / r.b.w;
-        }
-        __syncthreads();
-        for (int k = cnt - 1; k >= 0; --k) {
-            const uint32_t pos = lo + k - start;   // position in the tile list
-            float du = 0.f, dv = 0.f, da = 0.f, db = 0.f, dc = 0.f, dop = 0.f;
-            float dr = 0.f, dg = 0.f, dbl = 0.f;
-            bool hit = false;
-            if (inside && pos < last) {
-                const float2 c = s_xy[k];
-                const float4 q = s_cn[k];
-                const float dx = fx - c.x, dy = fy - c.y;
-                const float raw = __builtin_amdgcn_exp2f(gauss_exp2(q, dx, dy));   // opacity x G
-                const float alpha = fminf(amax, raw);
-                if (alpha >= amin) {
-                    hit = true;
-                    const float4 col = s_rgb[k];
-                    T = T / (1.0f - alpha);               // transmittance in front of i
-                    const float w = alpha * T;
-                    dr = w * g0;
-                    dg = w * g1;
-                    dbl = w * g2;
-                    const float cg = col.x * g0 + col.y * g1 + col.z * g2;
-                    const float sg = S0 * g0 + S1 * g1 + S2 * g2;
-                    const float dalpha = T * cg - (sg + bgdot) / (1.0f - alpha);
-                    S0 += col.x * w;
-                    S1 += col.y * w;
-                    S2 += col.z * w;
-                    if (raw < amax) {
-                        // power = -1/2 (a dx^2 + 2 b dx dy + c dy^2); alpha = opacity exp(power)
-                        dop = raw * s_io[k] * dalpha;                 // G = raw / opacity
-                        const float dpow = alpha * dalpha;   // d alpha / d power
-                        da = -0.5f * dx * dx * dpow;
-                        db = -dx * dy * dpow;
-                        dc = -0.5f * dy * dy * dpow;
-                        du = -kLn2 * (2.0f * q.x * dx + q.y * dy) * dpow;   // = (a dx + b dy) dpow
-                        dv = -kLn2 * (q.y * dx + 2.0f * q.z * dy) * dpow;   // = (b dx + c dy) dpow
-                    }
-                }
-            }
-            if (__ballot(hit) != 0ull) {
-                // wave sums (DPP, total in lane 63), then one LDS add per wave
-                du = wave_sum_to_last(du);
-                dv = wave_sum_to_last(dv);
-                da = wave_sum_to_last(da);
-                db = wave_sum_to_last(db);
-                dc = wave_sum_to_last(dc);
-                dop = wave_sum_to_last(dop);
-                dr = wave_sum_to_last(dr);
-                dg = wave_sum_to_last(dg);
-                dbl = wave_sum_to_last(dbl);
-                if (lane == 63) {
-                    float *acc = s_acc + k * 9;
-                    atomicAdd(acc + 0, du);
-                    atomicAdd(acc + 1, dv);
-                    atomicAdd(acc + 2, da);
-                    atomicAdd(acc + 3, db);
-                    atomicAdd(acc + 4, dc);
-                    atomicAdd(acc + 5, dop);
-                    atomicAdd(acc + 6, dr);
-                    atomicAdd(acc + 7, dg);
-                    atomicAdd(acc + 8, dbl);
-                }
-            }
-        }
-        __syncthreads();
-        // one global add per (Gaussian, value) for the whole tile
-        for (int j = threadIdx.x; j < cnt * 9; j += NT) {
-            const float v = s_acc[j];
-            if (v != 0.0f) atomicAdd(a.g2d + (int64_t)s_id[j / 9] * 9 + (j % 9), v);
-            s_acc[j] = 0.0f;
-        }
-    }
-}
-
 // Workgroups of one kernel that fit on the device at once.
 template <typename K>
 int resident_groups(K kernel, int threads) {
@@ -498,37 +328,7 @@ void launch_fwd(const CompArgs &a, int n_tiles, hipStream_t s) {
     }
 }
 
-template <int TW, int TH, int BATCH>
-void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, s, a);
-}
-
 }  // namespace
-
-#define FDGS_DISPATCH(LAUNCH, ARGS)                                                             \
-    do {                                                                                        \
-        const int key = rp.tile_w * 1000 + rp.tile_h;                                           \
-        bool ok = true;                                                                         \
-        if (key == 8008) {                                                                      \
-            if (batch == 64) LAUNCH<8, 8, 64>(ARGS, n_tiles, s);                                \
-            else if (batch == 128) LAUNCH<8, 8, 128>(ARGS, n_tiles, s);                         \
-            else if (batch == 256) LAUNCH<8, 8, 256>(ARGS, n_tiles, s);                         \
-            else ok = false;                                                                    \
-        } else if (key == 16016) {                                                              \
-            if (batch == 64) LAUNCH<16, 16, 64>(ARGS, n_tiles, s);                              \
-            else if (batch == 128) LAUNCH<16, 16, 128>(ARGS, n_tiles, s);                       \
-            else if (batch == 256) LAUNCH<16, 16, 256>(ARGS, n_tiles, s);                       \
-            else ok = false;                                                                    \
-        } else if (key == 32008) {                                                              \
-            if (batch == 64) LAUNCH<32, 8, 64>(ARGS, n_tiles, s);                               \
-            else if (batch == 128) LAUNCH<32, 8, 128>(ARGS, n_tiles, s);                        \
-            else if (batch == 256) LAUNCH<32, 8, 256>(ARGS, n_tiles, s);                        \
-            else ok = false;                                                                    \
-        } else {                                                                                \
-            ok = false;                                                                         \
-        }                                                                                       \
-        if (!ok) return hipErrorInvalidValue;                                                   \
-    } while (0)
 
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
                             const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
@@ -548,17 +348,6 @@ hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_
 
 hipError_t launch_flags_to_bits(const uint8_t *flags, int64_t n, uint32_t *bits, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(flags_to_bits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, flags, n, bits);
-    return hipGetLastError();
-}
-
-hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
-                                     const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
-                                     const float *T_final, const uint32_t *n_contrib,
-                                     const float *dL_drgb, float *g2d, int64_t /*n_proc_max*/,
-                                     hipStream_t s) {
-    BwdArgs a{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d};
-    const int n_tiles = rp.tiles_x * rp.tiles_y;
-    FDGS_DISPATCH(launch_bwd, a);
     return hipGetLastError();
 }
 

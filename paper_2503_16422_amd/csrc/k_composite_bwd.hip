@@ -1,0 +1,199 @@
+// Adjoint of the per-tile compositing (Eq. 2 and Eq. 3 differentiated with
+// respect to each record's centre, conic, opacity and colour).
+#include <hip/hip_runtime.h>
+
+#include "dev_composite.h"
+#include "dev_util.h"
+#include "fdgs_internal.h"
+
+namespace fdgs {
+namespace {
+
+using namespace comp;
+
+struct BwdArgs {
+    RenderParams rp;
+    int32_t W, H;
+    const uint32_t *ranges;
+    const uint32_t *ids;
+    const Rec2D *rec;
+    const float *T_final;
+    const uint32_t *n_contrib;
+    const float *dL;
+    float *g2d;        // [n_proc][9]: du, dv, d conic a, b, c, d opacity, d rgb
+};
+
+// Adjoint, walking each pixel's list back to front from its last contributor.
+// The transmittance in front of Gaussian i is recovered as T_{i+1} / (1 - a_i)
+// from the stored final T, so no per-pixel list is kept.  With g = dL/dC and
+// S the colour accumulated behind i (absolute weights):
+//   dL/dc_i = a_i T_i g
+//   dL/da_i = T_i c_i.g - (S.g + T_final bg.g) / (1 - a_i)
+// then a_i = min(a_max, o_i G_i) -> (o_i, conic, centre).  A thread owns PPT
+// pixels of a column (as in the forward) and adds their terms before the
+// per-Gaussian sums are reduced across the wavefront (DPP, total in lane 63)
+// and added into the tile's LDS accumulators; one global add per value and
+// Gaussian leaves the tile after each batch.
+template <int TW, int TH, int BATCH, int PPT>
+__global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) {
+    constexpr int NT = TW * TH / PPT;
+    __shared__ float2 s_xy[BATCH];
+    __shared__ float4 s_cn[BATCH];    // staged conic and opacity, as in the forward
+    __shared__ float4 s_rgb[BATCH];
+    __shared__ uint32_t s_id[BATCH];
+    __shared__ float s_io[BATCH];     // 1 / opacity
+    __shared__ float s_acc[BATCH * 9]; // per-Gaussian gradient sums of the tile
+    const int tile = blockIdx.x;
+    const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
+    const int lx = threadIdx.x % TW, ly0 = (threadIdx.x / TW) * PPT;
+    const int px = tx * TW + lx, py0 = ty * TH + ly0;
+    const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;   // as in the forward
+    const float fx = (float)(px - bx0) + 0.5f;
+    const float ox = (float)bx0, oy = (float)by0;
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const float amin = a.rp.alpha_min, amax = a.rp.alpha_max;
+    const int64_t plane = (int64_t)a.W * a.H;
+    float fy[PPT], g0[PPT], g1[PPT], g2[PPT], T[PPT], S0[PPT], S1[PPT], S2[PPT], bgdot[PPT];
+    uint32_t last[PPT];
+    uint32_t my_max = 0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int py = py0 + p;
+        fy[p] = (float)(py - by0) + 0.5f;
+        g0[p] = g1[p] = g2[p] = 0.f;
+        T[p] = 1.f;
+        last[p] = 0;
+        if (px < a.W && py < a.H) {
+            const int64_t pix = (int64_t)py * a.W + px;
+            g0[p] = a.dL[pix];
+            g1[p] = a.dL[plane + pix];
+            g2[p] = a.dL[2 * plane + pix];
+            T[p] = a.T_final[pix];
+            last[p] = a.n_contrib[pix];
+        }
+        bgdot[p] = T[p] * (a.rp.bg[0] * g0[p] + a.rp.bg[1] * g1[p] + a.rp.bg[2] * g2[p]);   // T_final bg.g
+        S0[p] = S1[p] = S2[p] = 0.f;
+        my_max = max(my_max, last[p]);
+    }
+    // block-wide maximum of `last` bounds the walk
+    __shared__ uint32_t s_max;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    atomicMax(&s_max, my_max);
+    __syncthreads();
+    const uint32_t walk_end = start + s_max;
+    const int lane = lane_id();
+    for (int j = threadIdx.x; j < BATCH * 9; j += NT) s_acc[j] = 0.0f;
+    for (int64_t top = (int64_t)walk_end; top > (int64_t)start; top -= BATCH) {
+        const uint32_t lo = (uint32_t)max((int64_t)start, top - BATCH);
+        const int cnt = (int)(top - lo);
+        __syncthreads();
+        for (int k = threadIdx.x; k < cnt; k += NT) {
+            const uint32_t id = a.ids[lo + k];
+            const Rec2D r = a.rec[id];
+            s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
+            s_cn[k] = staged_conic(r);
+            s_rgb[k] = r.c;
+            s_id[k] = id;
+            s_io[k] = 1.0f / r.b.w;
+        }
+        __syncthreads();
+        for (int k = cnt - 1; k >= 0; --k) {
+            const uint32_t pos = lo + k - start;   // position in the tile list
+            const float2 c = s_xy[k];
+            const float4 q = s_cn[k];
+            const float dx = fx - c.x;
+            const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
+            float du = 0.f, dv = 0.f, da = 0.f, db = 0.f, dc = 0.f, dop = 0.f;
+            float dr = 0.f, dg = 0.f, dbl = 0.f;
+            bool hit = false;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                if (pos < last[p]) {
+                    const float dy = fy[p] - c.y;
+                    const float raw = __builtin_amdgcn_exp2f(exp2_at(q, A, B, dy));   // opacity x G
+                    const float alpha = fminf(amax, raw);
+                    if (alpha >= amin) {
+                        hit = true;
+                        const float4 col = s_rgb[k];
+                        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);   // 1 / (1 - a_i), ~1 ulp
+                        T[p] = T[p] * inv;                 // transmittance in front of i
+                        const float w = alpha * T[p];
+                        dr = fmaf(w, g0[p], dr);
+                        dg = fmaf(w, g1[p], dg);
+                        dbl = fmaf(w, g2[p], dbl);
+                        const float cg = col.x * g0[p] + col.y * g1[p] + col.z * g2[p];
+                        const float sg = S0[p] * g0[p] + S1[p] * g1[p] + S2[p] * g2[p];
+                        const float dalpha = T[p] * cg - (sg + bgdot[p]) * inv;
+                        S0[p] += col.x * w;
+                        S1[p] += col.y * w;
+                        S2[p] += col.z * w;
+                        if (raw < amax) {
+                            // power = -1/2 (a dx^2 + 2 b dx dy + c dy^2); alpha = opacity exp(power)
+                            dop = fmaf(raw * s_io[k], dalpha, dop);       // G = raw / opacity
+                            const float dpow = alpha * dalpha;   // d alpha / d power
+                            da = fmaf(-0.5f * dx * dx, dpow, da);
+                            db = fmaf(-dx * dy, dpow, db);
+                            dc = fmaf(-0.5f * dy * dy, dpow, dc);
+                            du = fmaf(-kLn2 * (2.0f * q.x * dx + q.y * dy), dpow, du);   // (a dx + b dy) dpow
+                            dv = fmaf(-kLn2 * (q.y * dx + 2.0f * q.z * dy), dpow, dv);   // (b dx + c dy) dpow
+                        }
+                    }
+                }
+            }
+            if (__ballot(hit) != 0ull) {
+                // wave sums (DPP, total in lane 63), then one LDS add per wave
+                du = wave_sum_to_last(du);
+                dv = wave_sum_to_last(dv);
+                da = wave_sum_to_last(da);
+                db = wave_sum_to_last(db);
+                dc = wave_sum_to_last(dc);
+                dop = wave_sum_to_last(dop);
+                dr = wave_sum_to_last(dr);
+                dg = wave_sum_to_last(dg);
+                dbl = wave_sum_to_last(dbl);
+                if (lane == 63) {
+                    float *acc = s_acc + k * 9;
+                    atomicAdd(acc + 0, du);
+                    atomicAdd(acc + 1, dv);
+                    atomicAdd(acc + 2, da);
+                    atomicAdd(acc + 3, db);
+                    atomicAdd(acc + 4, dc);
+                    atomicAdd(acc + 5, dop);
+                    atomicAdd(acc + 6, dr);
+                    atomicAdd(acc + 7, dg);
+                    atomicAdd(acc + 8, dbl);
+                }
+            }
+        }
+        __syncthreads();
+        // one global add per (Gaussian, value) for the whole tile
+        for (int j = threadIdx.x; j < cnt * 9; j += NT) {
+            const float v = s_acc[j];
+            if (v != 0.0f) atomicAdd(a.g2d + (int64_t)s_id[j / 9] * 9 + (j % 9), v);
+            s_acc[j] = 0.0f;
+        }
+    }
+}
+
+// Pixels per thread in the adjoint: 2 for the 256-pixel tiles, 1 for 8x8.
+template <int TW, int TH, int BATCH>
+void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
+    constexpr int PPT = TW * TH > 64 ? 2 : 1;
+    hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, BATCH, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
+}
+
+}  // namespace
+
+hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+                                     const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                                     const float *T_final, const uint32_t *n_contrib,
+                                     const float *dL_drgb, float *g2d, int64_t /*n_proc_max*/,
+                                     hipStream_t s) {
+    BwdArgs a{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d};
+    const int n_tiles = rp.tiles_x * rp.tiles_y;
+    FDGS_DISPATCH(launch_bwd, a);
+    return hipGetLastError();
+}
+
+}  // namespace fdgs

@@ -106,7 +106,7 @@ hipError_t scan_impl(Load ld, Out *out, const int64_t *n_dev, int64_t n_max, int
 __global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *visible, const uint64_t *depth_key,
                                                               const int64_t *n_dev, int64_t n_max,
                                                               const uint64_t *partial, uint32_t *keys32,
-                                                              uint32_t *vals) {
+                                                              uint32_t *vals, uint32_t *asc) {
     __shared__ uint64_t tmp[kNT / 64 + 1];
     const int64_t n = count_of(n_dev, n_max);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
@@ -125,6 +125,7 @@ __global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *vis
             const double z = __longlong_as_double((long long)depth_key[base + k]);
             keys32[run] = __float_as_uint((float)z);   // z > 0: bit order = value order
             vals[run] = (uint32_t)(base + k);
+            if (asc) asc[run] = (uint32_t)(base + k);
             ++run;
         }
     }
@@ -194,7 +195,8 @@ hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t 
 }
 
 hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
-                           int64_t *total, uint32_t *keys32, uint32_t *vals, void *scratch, hipStream_t s) {
+                           int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, void *scratch,
+                           hipStream_t s) {
     const int64_t nb = (n_max + kChunk - 1) / kChunk;
     uint64_t *partial = static_cast<uint64_t *>(scratch);
     if (nb > 0)
@@ -203,7 +205,7 @@ hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, co
     hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total);
     if (nb > 0)
         hipLaunchKernelGGL(compact_visible_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, visible, depth_key, n_dev,
-                           n_max, (const uint64_t *)partial, keys32, vals);
+                           n_max, (const uint64_t *)partial, keys32, vals, asc);
     return hipGetLastError();
 }
 

@@ -218,9 +218,9 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
 // block then writes those instances with consecutive threads (runs of
 // kDupRun, one binary search over the rows per run), so the stores are
 // coalesced however the rows' lengths vary.  Counts and emission use the same
-// float arithmetic, so each Gaussian fills exactly its slots; tile
-// coordinates are clamped into the rectangle and writes into [first, last),
-// so keys, ids and addresses stay in range whatever the counts hold.
+// float arithmetic, so each Gaussian fills exactly its slots; a tile's column
+// is clamped into its row's span and writes into [first, last), so keys, ids
+// and addresses stay in range whatever the counts hold.
 constexpr int kDupNT = 256;
 constexpr int kDupRun = 8;
 
@@ -236,7 +236,8 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
     __shared__ uint32_t s_rbase[kDupNT + 1];     // first row of each Gaussian in the block's row list
     __shared__ uint32_t s_rpos[kDupNT + 1];      // per row of the chunk: first instance (block-relative)
     __shared__ uint32_t s_rkey[kDupNT];          // per row: key of its first tile
-    __shared__ uint16_t s_rg[kDupNT];            // per row: Gaussian (block-local)
+    __shared__ uint32_t s_rlen[kDupNT];          // per row: tiles in the row minus one
+    __shared__ uint32_t s_rid[kDupNT];           // per row: Gaussian position
     __shared__ uint32_t s_tmp[kDupNT / 64 + 1];
     const int64_t n_vis = count_of(n_vis_dev, n_max);
     const int64_t n_inst = *n_inst_dev;
@@ -266,15 +267,14 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
     uint64_t carry = first;
     for (uint32_t row0 = 0; row0 < n_rows_total; row0 += kDupNT) {
         const uint32_t rho = row0 + (uint32_t)t;
-        uint32_t n = 0, key0 = 0;
-        int g = 0;
+        uint32_t n = 0, key0 = 0, rid = 0;
         if (rho < n_rows_total) {
             int lo = 0, hi = cnt - 1;                  // largest g with s_rbase[g] <= rho
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_rbase[mid] <= rho) lo = mid; else hi = mid - 1;
             }
-            g = lo;
+            const int g = lo;
             const int4 r = s_rect[g];
             const int ty = r.y / rp.tile_h + (int)(rho - s_rbase[g]);
             int c0, c1;
@@ -282,12 +282,14 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
                 n = (uint32_t)(c1 - c0 + 1);
                 key0 = s_base[g] + (uint32_t)(ty * rp.tiles_x + c0);
             }
+            rid = s_id[g];
         }
         uint32_t chunk_total;
         const uint32_t pos = block_exclusive_sum<kDupNT>(n, s_tmp, &chunk_total);
         s_rpos[t] = pos;
         s_rkey[t] = key0;
-        s_rg[t] = (uint16_t)g;
+        s_rlen[t] = n ? n - 1u : 0u;
+        s_rid[t] = rid;
         if (t == 0) s_rpos[kDupNT] = chunk_total;
         __syncthreads();
         // instances [carry, carry + chunk_total): run e0 starts in the last row whose first instance is <= e0
@@ -303,16 +305,9 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
             for (uint64_t e = e0; e < e1; ++e) {
                 const uint32_t k = (uint32_t)(e - carry);
                 while (k >= s_rpos[lo + 1]) ++lo;     // s_rpos[kDupNT] = chunk_total > k ends this
-                const int gg = s_rg[lo];
-                const int4 r = s_rect[gg];
-                // clamp the tile into the Gaussian's rectangle (a no-op when counts agree)
-                const uint32_t base = s_base[gg];
-                const uint32_t key = s_rkey[lo] + (k - s_rpos[lo]);
-                const int tile = (int)(key - base);
-                const int ty = min(max(tile / rp.tiles_x, r.y / rp.tile_h), r.w / rp.tile_h);
-                const int tx = min(max(tile - (tile / rp.tiles_x) * rp.tiles_x, r.x / rp.tile_w), r.z / rp.tile_w);
-                tile_keys[e] = base + (uint32_t)(ty * rp.tiles_x + tx);
-                ids[e] = s_id[gg];
+                // the column offset is clamped to the row's span (a no-op when counts agree)
+                tile_keys[e] = s_rkey[lo] + min(k - s_rpos[lo], s_rlen[lo]);
+                ids[e] = s_rid[lo];
             }
         }
         carry += chunk_total;

@@ -261,8 +261,9 @@ class Context:
     def check_overflow(self):
         _lib.check(self.lib.fdgs_check_overflow(self.handle, _stream(self.device)))
 
-    def profile(self, enable: bool):
-        _lib.check(self.lib.fdgs_profile_enable(self.handle, 1 if enable else 0))
+    def profile(self, enable, count_pairs: bool = False):
+        level = 0 if not enable else (2 if count_pairs else 1)
+        _lib.check(self.lib.fdgs_profile_enable(self.handle, level))
 
     def profile_read(self, reset: bool = True) -> dict:
         p = _lib.Profile()
