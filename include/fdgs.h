@@ -303,6 +303,55 @@ FDGS_API fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int3
                                    hipStream_t stream);
 
 /*
+ * (7) Pruning with the spatial-temporal variation score (Sec. 4.2.1).
+ *
+ * fdgs_spatial_score (Eq. 4): for each v < n_views renders the model at
+ * (cams[v], times[v]) (host arrays) with every Gaussian processed and ADDS to
+ * inout_score[i] (device, float[n]) the sum over that view's pixels of
+ * Gaussian i's blend weight alpha_i T_i.  cfg may be NULL (defaults; its tile
+ * shape, batch and schedule only change speed).  Synchronises `stream`.
+ */
+FDGS_API fdgs_status fdgs_spatial_score(fdgs_ctx *ctx, const fdgs_model *model, const fdgs_camera *cams,
+                                        const double *times, int32_t n_views, const fdgs_render_cfg *cfg,
+                                        float *inout_score, hipStream_t stream);
+
+/*
+ * fdgs_variation_score (Eq. 5-7): out_score[i] = S^TV_i gamma_i spatial[i]
+ * (device float[n] in and out) with
+ *   S^TV_i  = sum over the n_times host times t of 1 / (0.5 tanh|p_i''(t)| + 0.5),
+ *             p_i''(t) = ((t - mu_t)^2 / Sigma_44^2 - 1 / Sigma_44) p_i(t),
+ *   gamma_i = min(V_i / V_90, 1)^0.1, V_i = product of the four scales and V_90
+ *             the volume at position floor(0.9 (n - 1)) of the ascending volumes
+ *             (gamma = 1 for every positive volume if V_90 = 0);
+ * invalid Gaussians score 0.  Temporal sums in float64.  Synchronises `stream`.
+ */
+FDGS_API fdgs_status fdgs_variation_score(fdgs_ctx *ctx, const fdgs_model *model, const double *times,
+                                          int32_t n_times, const float *spatial, float *out_score,
+                                          hipStream_t stream);
+
+/*
+ * fdgs_prune: keeps the n_keep (0..n) highest of score[0..n) (device), equal
+ * scores by the lower index, negative or NaN scores counting as 0, and writes
+ * the kept set as fdgs_build_active_mask does: out_bits[ceil(n/32)],
+ * out_idx[n] (ascending; entries past the count unspecified), *out_count.
+ * Synchronises `stream`.
+ */
+FDGS_API fdgs_status fdgs_prune(fdgs_ctx *ctx, const float *score, int64_t n, int64_t n_keep, uint32_t *out_bits,
+                                uint32_t *out_idx, int64_t *out_count, hipStream_t stream);
+
+/*
+ * (8) Adam step for fine-tuning the kept Gaussians: for i < n (device float
+ * arrays, updated in place)
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * step >= 1; m and v start at 0.  Elements with g = 0 and m = v = 0 (never
+ * touched by a gradient) stay unchanged.
+ */
+FDGS_API fdgs_status fdgs_adam_step(fdgs_ctx *ctx, float *param, const float *grad, float *m, float *v, int64_t n,
+                                    float lr, float beta1, float beta2, float eps, int32_t step,
+                                    hipStream_t stream);
+
+/*
  * Reports FDGS_ERR_CAPACITY if a forward with a fixed instance_capacity on
  * this context overflowed since the last check, or FDGS_ERR_UNSUPPORTED if
  * more than 4096 visible Gaussians of one forward shared a float32-rounded

@@ -22,6 +22,9 @@
  * contributors whose depths differ, but by at most rel_depth * depth (exactly
  * equal depths are ordered by index, which is not ambiguous).
  *
+ * Blend weights (optional, per Gaussian, summed over pixels): alpha_i T_i of
+ * every blend, the ray contribution that Eq. 4 sums over all pixels.
+ *
  * Contributions (optional, per Gaussian, OR-ed over pixels): 1 blended at a
  * pixel whose flags were still 0 after this Gaussian's own decisions (a float32
  * renderer takes the same decisions, so it blends it too); 2 blended at some
@@ -37,6 +40,7 @@ typedef struct {
     const double *u, *v, *ca, *cb, *cc, *opac, *rgb, *depth; /* rgb: n x 3 */
     const int32_t *rect;                                     /* n x 4 (x0,y0,x1,y1) or NULL */
     int32_t *contrib;                                        /* n, OR-ed contribution bits, or NULL */
+    double *weight;                                          /* n, summed alpha T, or NULL */
     double bg[3];
     double alpha_min, alpha_max, t_min;
     double rel_alpha, rel_t, rel_depth;
@@ -76,6 +80,10 @@ static void shade_pixel(const oracle_scene *s, const int64_t *list, int64_t nlis
             s->contrib[i] |= bits;
         }
         const double w = alpha * T;
+        if (s->weight) {
+            #pragma omp atomic update
+            s->weight[i] += w;
+        }
         C0 += s->rgb[3 * i + 0] * w;
         C1 += s->rgb[3 * i + 1] * w;
         C2 += s->rgb[3 * i + 2] * w;

@@ -163,7 +163,7 @@ def composite_py(pre: Prepared, order, px, py, st: Settings):
 
 class _Scene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in
-                ("u", "v", "ca", "cb", "cc", "opac", "rgb", "depth", "rect", "contrib")] + [
+                ("u", "v", "ca", "cb", "cc", "opac", "rgb", "depth", "rect", "contrib", "weight")] + [
                 ("bg", ctypes.c_double * 3), ("alpha_min", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double),
                 ("rel_alpha", ctypes.c_double), ("rel_t", ctypes.c_double),
@@ -195,18 +195,21 @@ class Image:
     T: np.ndarray
     flags: np.ndarray
     contrib: np.ndarray = None   # int32 per processed Gaussian: 1 surely blended, 2 possibly blended
+    weight: np.ndarray = None    # float64 per processed Gaussian: summed alpha T over the pixels
 
 
 def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=None,
               rel_alpha: float = 1e-5, rel_t: float = 1e-4, rel_depth: float = 1e-12,
-              contributions: bool = False) -> Image:
+              contributions: bool = False, weights: bool = False) -> Image:
     """Shade the full image (pixels=None) or the given (px, py) arrays.
 
     mode "brute": every alive Gaussian at every pixel; "rect": skip outside the
     conservative rectangle (identical result).  contributions: also return,
     per processed Gaussian, whether some pixel blends it (Eq. 2): bit 1 when a
     pixel does so with every decision so far clear of the thresholds, bit 2
-    when a pixel does or, at a flagged pixel, may.
+    when a pixel does or, at a flagged pixel, may.  weights: also return, per
+    processed Gaussian, the sum over the shaded pixels of its blend weight
+    alpha_i T_i (the summand of Eq. 4).
     """
     order = depth_order(pre, use_visible=False)
     keep = np.ones(order.shape, dtype=bool)
@@ -243,6 +246,8 @@ def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=No
     s.opac, s.rgb, s.depth, s.rect = ptr(opac), ptr(rgb), ptr(depth), ptr(rect)
     contrib = np.zeros(order.shape[0], dtype=np.int32) if contributions else None
     s.contrib = ptr(contrib)
+    weight = np.zeros(order.shape[0]) if weights else None
+    s.weight = ptr(weight)
     for k in range(3):
         s.bg[k] = float(st.bg[k])
     s.alpha_min, s.alpha_max, s.t_min = st.alpha_min, st.alpha_max, st.t_min
@@ -257,14 +262,17 @@ def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=No
     inv = np.empty_like(perm)
     inv[perm] = np.arange(npix)
     rgb_o, t_o, f_o = out_rgb[inv].T, out_t[inv], out_f[inv]
-    per_gauss = None
+    per_gauss = per_w = None
     if contributions:
         per_gauss = np.zeros(pre.visible.shape[0], dtype=np.int32)
         per_gauss[order] = contrib
+    if weights:
+        per_w = np.zeros(pre.visible.shape[0])
+        per_w[order] = weight
     if full:
         H, W = cam.height, cam.width
-        return Image(rgb_o.reshape(3, H, W), t_o.reshape(H, W), f_o.reshape(H, W), per_gauss)
-    return Image(rgb_o, t_o, f_o, per_gauss)
+        return Image(rgb_o.reshape(3, H, W), t_o.reshape(H, W), f_o.reshape(H, W), per_gauss, per_w)
+    return Image(rgb_o, t_o, f_o, per_gauss, per_w)
 
 
 def render(scene_arrays, cam, t: float, st: Settings = None, *, idx=None, mode="rect",

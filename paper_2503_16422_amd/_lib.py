@@ -25,7 +25,8 @@ MASK_CONTRIBUTED = 2
 EXPORTS = ["fdgs_last_error", "fdgs_version", "fdgs_create", "fdgs_destroy", "fdgs_render_cfg_default",
            "fdgs_slice_4d", "fdgs_build_active_mask", "fdgs_render_forward", "fdgs_render_backward",
            "fdgs_state_release", "fdgs_state_binning", "fdgs_check_overflow", "fdgs_profile_enable",
-           "fdgs_profile_read", "fdgs_render_batch", "fdgs_autotune"]
+           "fdgs_profile_read", "fdgs_render_batch", "fdgs_autotune", "fdgs_spatial_score",
+           "fdgs_variation_score", "fdgs_prune", "fdgs_adam_step"]
 
 STAGES = ["preprocess", "compact", "depth_sort", "offsets", "duplicate", "tile_sort", "ranges", "composite",
           "bwd_composite", "bwd_preprocess"]

@@ -131,6 +131,7 @@ struct fdgs_ctx {
     Buf overflow;                  // int32 device flag
     Buf mask_frames, mask_views, mask_scratch;
     Buf mask_flags, mask_img;      // contributed-mode visibility bytes and the keyframe image
+    Buf prune_a, prune_b, prune_c, prune_d, prune_e, prune_times;   // score / prune work
     int64_t *host_counts = nullptr;  // pinned
     // profiling
     int prof = 0;                  // 0 off, 1 stage events and counts, 2 also evaluated pairs
@@ -253,6 +254,8 @@ fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
     release(ctx->mask_scratch);
     release(ctx->mask_flags);
     release(ctx->mask_img);
+    for (Buf *b : {&ctx->prune_a, &ctx->prune_b, &ctx->prune_c, &ctx->prune_d, &ctx->prune_e, &ctx->prune_times})
+        release(*b);
     release(ctx->prof_acc);
     for (auto &p : ctx->pending) {
         (void)hipEventDestroy(p.e0);
@@ -347,7 +350,7 @@ fdgs_state *find_state(fdgs_ctx *ctx, fdgs_state *s) {
 fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const ViewDesc *table, int32_t V,
                         const int64_t *n_dev, int64_t n_total, int32_t W, int32_t H, const fdgs_render_cfg *cfg,
                         float *out_rgb, float *out_T, bool need_state, hipStream_t stream,
-                        uint8_t *contrib = nullptr);
+                        uint8_t *contrib = nullptr, float *weight = nullptr);
 
 }  // namespace
 
@@ -493,7 +496,8 @@ RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
 // buffers are already large enough and a fixed instance capacity is given.
 fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const ViewDesc *table, int32_t V,
                         const int64_t *n_dev, int64_t n_total, int32_t W, int32_t H, const fdgs_render_cfg *cfg,
-                        float *out_rgb, float *out_T, bool need_state, hipStream_t stream, uint8_t *contrib) {
+                        float *out_rgb, float *out_T, bool need_state, hipStream_t stream, uint8_t *contrib,
+                        float *weight) {
     const char *fn = "fdgs_render";
     const RenderParams rp = make_params(cfg, W, H);
     const int64_t tiles_per_view = (int64_t)rp.tiles_x * rp.tiles_y;
@@ -611,7 +615,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
                                  S->rect.as<int32_t>(), out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
                                  acc && ctx->prof == 2 ? acc + 3 : nullptr,
                                  cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt,
-                                 cfg->schedule ? S->sched.as<uint32_t>() : nullptr, contrib, stream));
+                                 cfg->schedule ? S->sched.as<uint32_t>() : nullptr, contrib, weight, stream));
     }
     if (need_state && out_T)
         HIP_TRY(hipMemcpyAsync(out_T, S->T_final.p, sizeof(float) * npx, hipMemcpyDeviceToDevice, stream));
@@ -1015,6 +1019,126 @@ fdgs_status fdgs_profile_read(fdgs_ctx *ctx, fdgs_profile *out, int32_t reset) {
             ctx->calls[k] = 0;
         }
     }
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_spatial_score(fdgs_ctx *ctx, const fdgs_model *model, const fdgs_camera *cams, const double *times,
+                               int32_t n_views, const fdgs_render_cfg *cfg, float *inout_score, hipStream_t stream) {
+    const char *fn = "fdgs_spatial_score";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (fdgs_status st = check_model(model, fn)) return st;
+    if (n_views < 0 || (n_views > 0 && (!cams || !times)))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: need n_views >= 0 cameras and times", fn);
+    fdgs_render_cfg c;
+    if (cfg) {
+        if (fdgs_status st = check_cfg(cfg, fn)) return st;
+        c = *cfg;
+    } else {
+        fdgs_render_cfg_default(&c);
+        c.pixels_per_thread = 2;
+    }
+    c.instance_capacity = 0;
+    if (c.tile_w * c.tile_h == 64) c.pixels_per_thread = 1;
+    if (model->n > 0 && !inout_score) return fail(FDGS_ERR_INVALID_ARG, "%s: inout_score is NULL", fn);
+    for (int v = 0; v < n_views; ++v) {
+        if (fdgs_status st = check_camera(&cams[v], fn)) return st;
+        if (!std::isfinite(times[v])) return fail(FDGS_ERR_INVALID_ARG, "%s: view %d time not finite", fn, v);
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    int64_t px_max = 1;
+    for (int v = 0; v < n_views; ++v) px_max = std::max<int64_t>(px_max, (int64_t)cams[v].width * cams[v].height);
+    HIP_TRY(ensure(ctx->mask_img, sizeof(float) * 3 * (size_t)px_max));
+    for (int v = 0; v < n_views; ++v) {
+        ViewDesc one;
+        one.m = kmodel(model);
+        one.cam = kcam(&cams[v]);
+        one.t = times[v];
+        one.idx = nullptr;
+        one.p_off = 0;
+        one.n_proc = model->n;
+        if (fdgs_status st = run_forward(ctx, &ctx->scratch_state, &one, nullptr, 1, nullptr, model->n, cams[v].width,
+                                         cams[v].height, &c, ctx->mask_img.as<float>(), nullptr, false, stream,
+                                         nullptr, inout_score))
+            return st;
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_variation_score(fdgs_ctx *ctx, const fdgs_model *model, const double *times, int32_t n_times,
+                                 const float *spatial, float *out_score, hipStream_t stream) {
+    const char *fn = "fdgs_variation_score";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (fdgs_status st = check_model(model, fn)) return st;
+    if (n_times < 0 || (n_times > 0 && !times)) return fail(FDGS_ERR_INVALID_ARG, "%s: bad times", fn);
+    for (int f = 0; f < n_times; ++f)
+        if (!std::isfinite(times[f])) return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite time", fn);
+    const int64_t n = model->n;
+    if (n > 0 && (!spatial || !out_score)) return fail(FDGS_ERR_INVALID_ARG, "%s: a score pointer is NULL", fn);
+    if (n == 0) return FDGS_OK;
+    if (n >= (int64_t(1) << 32)) return fail(FDGS_ERR_INVALID_ARG, "%s: n too large", fn);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(ensure(ctx->prune_times, sizeof(double) * std::max(1, n_times)));
+    if (n_times > 0)
+        HIP_TRY(hipMemcpyAsync(ctx->prune_times.p, times, sizeof(double) * n_times, hipMemcpyHostToDevice, stream));
+    HIP_TRY(ensure(ctx->prune_a, sizeof(float) * n));      // S^TV
+    HIP_TRY(ensure(ctx->prune_b, sizeof(uint32_t) * n));   // volume keys
+    HIP_TRY(ensure(ctx->prune_c, sizeof(uint32_t) * n));   // values
+    HIP_TRY(ensure(ctx->prune_d, sizeof(uint32_t) * 3 * n));   // sort ping-pong (keys, values) and a copy
+    HIP_TRY(ensure(ctx->prune_e, sort_scratch_bytes(n)));
+    uint32_t *vk = ctx->prune_b.as<uint32_t>(), *vv = ctx->prune_c.as<uint32_t>();
+    uint32_t *k2 = ctx->prune_d.as<uint32_t>(), *v2 = k2 + n, *keep_keys = v2 + n;
+    HIP_TRY(launch_temporal_volume(kmodel(model), ctx->prune_times.as<double>(), n_times, ctx->prune_a.as<float>(),
+                                   vk, vv, stream));
+    HIP_TRY(hipMemcpyAsync(keep_keys, vk, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, stream));
+    int alt = 0;
+    HIP_TRY(radix_sort_u32(vk, vv, k2, v2, nullptr, n, 0, 32, ctx->prune_e.p, &alt, stream));
+    const uint32_t *sorted = alt ? k2 : vk;
+    const int64_t q = (int64_t)std::floor(0.9 * (double)(n - 1));
+    HIP_TRY(launch_variation_score(ctx->prune_a.as<float>(), keep_keys, sorted, n, q, spatial, out_score, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_prune(fdgs_ctx *ctx, const float *score, int64_t n, int64_t n_keep, uint32_t *out_bits,
+                       uint32_t *out_idx, int64_t *out_count, hipStream_t stream) {
+    const char *fn = "fdgs_prune";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (n < 0 || n >= (int64_t(1) << 32)) return fail(FDGS_ERR_INVALID_ARG, "%s: n out of range", fn);
+    if (n_keep < 0 || n_keep > n) return fail(FDGS_ERR_INVALID_ARG, "%s: n_keep out of range", fn);
+    if (!out_bits || !out_idx || !out_count || (n > 0 && !score))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: a pointer is NULL", fn);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(ensure(ctx->prune_b, sizeof(uint32_t) * std::max<int64_t>(n, 1)));
+    HIP_TRY(ensure(ctx->prune_c, sizeof(uint32_t) * std::max<int64_t>(n, 1)));
+    HIP_TRY(ensure(ctx->prune_d, sizeof(uint32_t) * 3 * std::max<int64_t>(n, 1)));
+    HIP_TRY(ensure(ctx->prune_e, std::max(sort_scratch_bytes(n), compact_scratch_bytes(n))));
+    HIP_TRY(ensure(ctx->mask_flags, (size_t)((n + 3) / 4) * 4 + 4));
+    uint32_t *keys = ctx->prune_b.as<uint32_t>(), *vals = ctx->prune_c.as<uint32_t>();
+    uint32_t *k2 = ctx->prune_d.as<uint32_t>(), *v2 = k2 + n;
+    HIP_TRY(launch_fill_u32(ctx->mask_flags.as<uint32_t>(), (n + 3) / 4, 0u, stream));
+    HIP_TRY(launch_prune_keys(score, n, keys, vals, stream));
+    int alt = 0;
+    HIP_TRY(radix_sort_u32(keys, vals, k2, v2, nullptr, n, 0, 32, ctx->prune_e.p, &alt, stream));
+    HIP_TRY(launch_mark_first(alt ? v2 : vals, n_keep, ctx->mask_flags.as<uint8_t>(), stream));
+    HIP_TRY(launch_flags_to_bits(ctx->mask_flags.as<uint8_t>(), n, out_bits, stream));
+    HIP_TRY(compact_bits(out_bits, n, out_idx, out_count, ctx->prune_e.p, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_adam_step(fdgs_ctx *ctx, float *param, const float *grad, float *m, float *v, int64_t n, float lr,
+                           float beta1, float beta2, float eps, int32_t step, hipStream_t stream) {
+    const char *fn = "fdgs_adam_step";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (n < 0) return fail(FDGS_ERR_INVALID_ARG, "%s: n < 0", fn);
+    if (n > 0 && (!param || !grad || !m || !v)) return fail(FDGS_ERR_INVALID_ARG, "%s: a pointer is NULL", fn);
+    if (step < 1) return fail(FDGS_ERR_INVALID_ARG, "%s: step must be >= 1", fn);
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+        !std::isfinite(lr))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: need 0 <= beta < 1, eps > 0, finite lr", fn);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, stream));
     return FDGS_OK;
 }
 

@@ -5,40 +5,9 @@
 #include <stdint.h>
 
 #include "../../include/fdgs.h"
+#include "kernel_types.h"
 
 namespace fdgs {
-
-// Camera as passed to kernels (by value).
-struct KCam {
-    double R[9];
-    double t[3];
-    double fx, fy, cx, cy, znear;
-    int32_t W, H;
-};
-
-// Model pointers as passed to kernels.
-struct KModel {
-    const float *mean, *log_scale, *q_left, *q_right, *logit, *sh;
-    int64_t n;
-    int32_t sh_degree;
-};
-
-// Per visible Gaussian record consumed by the compositor (48 B, 16-B aligned).
-//   a: u_hi, v_hi, u_lo, v_lo    (pixel-space centre as a float pair)
-//   b: conic a, b, c, opacity    (Sigma_2D^{-1} = [[a, b], [b, c]]; sigma * p(t))
-//   c: r, g, b, depth (float32)
-struct alignas(16) Rec2D {
-    float4 a, b, c;
-};
-
-struct RenderParams {
-    int32_t tile_w, tile_h, tiles_x, tiles_y;
-    float bg[3];
-    float alpha_min, alpha_max, t_min, dilation;
-    int32_t temporal_cull;
-    int32_t tile_cull;      // list a record only in the tiles its ellipse reaches
-    double vanilla_level;   // cut level without opacity culling, incl. margin
-};
 
 // Launch wrappers (each .hip file owns its kernels).  All are asynchronous.
 hipError_t launch_slice(const KModel &m, double t, const uint32_t *idx, int64_t count,
@@ -136,12 +105,13 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 // V * n_tiles + 1 uint32 of scratch: the items are ordered longest list first
 // and taken by persistent workgroups.
 // contrib (optional): contrib[id] = 1 for every processed entry some pixel
-// blends (state and counters are then not recorded).
+// blends; weight (optional): weight[id] += the entry's summed blend weights
+// alpha T (state and counters are not recorded in either case).
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
                             const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
                             uint64_t *pair_counter, int32_t pixels_per_thread, uint32_t *sched,
-                            uint8_t *contrib, hipStream_t s);
+                            uint8_t *contrib, float *weight, hipStream_t s);
 // bits[w] bit j = (flags[32 w + j] != 0), j < 32, for n flags.
 hipError_t launch_flags_to_bits(const uint8_t *flags, int64_t n, uint32_t *bits, hipStream_t s);
 
@@ -156,5 +126,17 @@ hipError_t launch_preprocess_backward(const KModel &m, const uint32_t *idx, cons
                                       const RenderParams &rp, const uint32_t *vis_list,
                                       const int64_t *n_vis_dev, const float *g2d, const fdgs_grads &grads,
                                       hipStream_t s);
+
+// Pruning score helpers (k_prune.hip).
+hipError_t launch_temporal_volume(const KModel &m, const double *times, int32_t n_times, float *tv,
+                                  uint32_t *vol_key, uint32_t *vals, hipStream_t s);
+hipError_t launch_variation_score(const float *tv, const uint32_t *vol_key, const uint32_t *sorted_vol, int64_t n,
+                                  int64_t q, const float *spatial, float *out, hipStream_t s);
+hipError_t launch_prune_keys(const float *score, int64_t n, uint32_t *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_mark_first(const uint32_t *sorted_vals, int64_t n_keep, uint8_t *flags, hipStream_t s);
+
+// Adam (k_optim.hip).
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                       float eps, int32_t step, hipStream_t s);
 
 }  // namespace fdgs

@@ -41,6 +41,7 @@ struct CompArgs {
     uint32_t *work_counter;      // persistent schedule: next item to take (zeroed by the ordering kernel)
     int32_t n_items;             // V x tiles per view
     uint8_t *contrib;            // kMark: per processed entry, set to 1 when blended
+    float *weight;               // kWeight: per processed entry, += sum of alpha T
 };
 
 // Thread layout: PPT consecutive pixels of one column per thread
@@ -52,6 +53,7 @@ enum CompMode {
     kState = 1,   // last contributor per pixel (for the adjoint)
     kCount = 2,   // last contributor and the evaluated-pair count (profiling)
     kMark = 3,    // flags every record some pixel blends (visibility masks)
+    kWeight = 4,  // adds every record's blend weights alpha T over the pixels (pruning score)
 };
 
 // One (view, tile) item; s_rec is the workgroup's LDS staging array of
@@ -77,6 +79,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     constexpr bool COUNT = MODE == kCount;
     constexpr bool LAST = MODE == kState || MODE == kCount;
     constexpr bool MARK = MODE == kMark;
+    constexpr bool WEIGHT = MODE == kWeight;
     constexpr float kInf = __builtin_huge_valf();
     // thr[p]: the transmittance a blend must keep; t_min while the pixel is
     // live, +inf once it has stopped (or lies outside the image), so a stopped
@@ -142,6 +145,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                         if (lane_id() == __builtin_ctzll(__ballot(1)))
                             a.contrib[__float_as_uint(s_rec[3 * k + 2].y)] = 1;
                     }
+                    if constexpr (WEIGHT) atomicAdd(&a.weight[__float_as_uint(s_rec[3 * k + 2].y)], w);
                 }
             } else {
                 // several pixels: select-based updates, no branches or lane masks per pixel;
@@ -157,6 +161,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                         const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
                         const uint32_t pos = base + k - start + 1;
                         bool blended = false;
+                        float wsum = 0.0f;
 #pragma unroll
                         for (int p = 0; p < PPT; ++p) {
                             // alpha below alpha_min enters as 0: the test then keeps T (>= t_min), w = 0
@@ -174,6 +179,13 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                             T[p] = ok ? test : T[p];
                             thr[p] = ok ? thr[p] : kInf;
                             if constexpr (MARK) blended = blended || w > 0.0f;
+                            if constexpr (WEIGHT) wsum += w;
+                        }
+                        if constexpr (WEIGHT) {
+                            // every lane is active here: one wave sum, one atomic per record and wave
+                            const float tot = wave_sum_to_last(wsum);
+                            if (lane_id() == 63 && tot != 0.0f)
+                                atomicAdd(&a.weight[__float_as_uint(s_rec[3 * k + 2].y)], tot);
                         }
                         if constexpr (MARK) {
                             const uint64_t m = __ballot(blended);
@@ -307,6 +319,8 @@ template <int TW, int TH, int BATCH, int PPT>
 void launch_fwd_ppt(const CompArgs &a, int n_tiles, hipStream_t s) {
     if (a.contrib)
         launch_fwd_sched<TW, TH, BATCH, PPT, kMark>(a, n_tiles, s);
+    else if (a.weight)
+        launch_fwd_sched<TW, TH, BATCH, PPT, kWeight>(a, n_tiles, s);
     else if (a.pairs)
         launch_fwd_sched<TW, TH, BATCH, PPT, kCount>(a, n_tiles, s);
     else if (a.n_contrib)
@@ -334,12 +348,13 @@ hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_
                             const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
                             uint64_t *pair_counter, int32_t ppt, uint32_t *sched, uint8_t *contrib,
-                            hipStream_t s) {
+                            float *weight, hipStream_t s) {
     if (ppt != 1 && ppt != 2 && ppt != 4) return hipErrorInvalidValue;
     const int n_tiles = rp.tiles_x * rp.tiles_y * V;
-    CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, contrib ? nullptr : n_contrib,
-               contrib ? nullptr : reinterpret_cast<unsigned long long *>(pair_counter), ppt, V,
-               sched, sched ? sched + n_tiles : nullptr, n_tiles, contrib};
+    const bool side = contrib || weight;   // visibility or score pass: no state, no counters
+    CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, side ? nullptr : n_contrib,
+               side ? nullptr : reinterpret_cast<unsigned long long *>(pair_counter), ppt, V,
+               sched, sched ? sched + n_tiles : nullptr, n_tiles, contrib, contrib ? nullptr : weight};
     if (sched) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderNT), 0, s, ranges, n_tiles, sched,
                                   sched + n_tiles);
     FDGS_DISPATCH(launch_fwd, a);

@@ -258,6 +258,39 @@ class Context:
         _lib.check(status)
         return best, out
 
+    # (7) pruning score ----------------------------------------------------
+    def spatial_score(self, model: GaussianModel, views, cfg: Optional[_lib.RenderCfg] = None,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """views: sequence of (camera, t).  Adds Eq. 4's per-Gaussian sums to `out`
+        (zeros if None) and returns it."""
+        score = out if out is not None else torch.zeros((model.n,), dtype=torch.float32, device=self.device)
+        cams = (_lib.Camera * max(len(views), 1))(*[_lib.camera_struct(v[0]) for v in views])
+        ts = np.ascontiguousarray(np.asarray([float(v[1]) for v in views], dtype=np.float64))
+        ms = model.struct()
+        _lib.check(self.lib.fdgs_spatial_score(self.handle, ctypes.byref(ms), cams, ts.ctypes.data_as(ctypes.c_void_p),
+                                               len(views), ctypes.byref(cfg) if cfg is not None else None,
+                                               _ptr(score), _stream(self.device)))
+        return score
+
+    def variation_score(self, model: GaussianModel, times, spatial: torch.Tensor) -> torch.Tensor:
+        out = torch.empty((model.n,), dtype=torch.float32, device=self.device)
+        ts = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        ms = model.struct()
+        _lib.check(self.lib.fdgs_variation_score(self.handle, ctypes.byref(ms), ts.ctypes.data_as(ctypes.c_void_p),
+                                                 ts.size, _ptr(spatial.contiguous()), _ptr(out),
+                                                 _stream(self.device)))
+        return out
+
+    def prune(self, score: torch.Tensor, n_keep: int):
+        n = int(score.numel())
+        bits = torch.empty(((n + 31) // 32 or 1,), dtype=torch.int32, device=self.device)
+        idx = torch.empty((max(n, 1),), dtype=torch.int32, device=self.device)
+        count = torch.zeros((1,), dtype=torch.int64, device=self.device)
+        _lib.check(self.lib.fdgs_prune(self.handle, _ptr(score.contiguous()), ctypes.c_int64(n),
+                                       ctypes.c_int64(int(n_keep)), _ptr(bits), _ptr(idx), _ptr(count),
+                                       _stream(self.device)))
+        return bits, idx, count
+
     def check_overflow(self):
         _lib.check(self.lib.fdgs_check_overflow(self.handle, _stream(self.device)))
 

@@ -53,6 +53,12 @@ def test_null_context_rejected_without_gpu(lib):
     assert lib.fdgs_build_active_mask(None, None, None, None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_state_release(None, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_check_overflow(None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_spatial_score(None, None, None, None, 0, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_variation_score(None, None, None, 0, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_prune(None, None, ctypes.c_int64(0), ctypes.c_int64(0), None, None, None,
+                          None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_adam_step(None, None, None, None, None, ctypes.c_int64(0), ctypes.c_float(0.1), ctypes.c_float(0.9),
+                              ctypes.c_float(0.999), ctypes.c_float(1e-8), 1, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_create(None, 0) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_destroy(None) == _lib.FDGS_OK
 

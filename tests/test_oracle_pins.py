@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import binning, mask, sh as osh
+from oracle import binning, mask, optim, prune, sh as osh
 from oracle import composite as oc
 from oracle import grad as og
 from oracle import slicing
@@ -531,6 +531,81 @@ def test_reached_tiles_of_a_thin_diagonal_ellipse():
     assert n_rect == 256 and tiles.size < 0.25 * n_rect
     diag = np.arange(16) * 16 + np.arange(16)
     assert np.all(np.isin(diag, tiles))
+
+
+# pruning score (Sec. 4.2.1) ---------------------------------------------------------------
+def test_spatial_score_sums_to_one_minus_final_transmittance():
+    """Per pixel the blend weights alpha_i T_i telescope to 1 - T_final, so the
+    spatial scores of one view sum to the image's sum of 1 - T; over several
+    views they add."""
+    sc = inputs.tiny_scene(2000, seed=5)
+    sc.log_scale[:3] += 0.7
+    st = oc.Settings()
+    views = [(inputs.look_at_camera(phi, 3.0, 40, 32), t) for phi, t in ((0.0, 0.5), (30.0, 0.45))]
+    total = 0.0
+    for cam, t in views:
+        s1 = prune.spatial_score(sc.arrays(), [(cam, t)], st)
+        img = oc.render(sc.arrays(), cam, t, st, mode="brute")
+        assert abs(s1.sum() - (1.0 - img.T).sum()) <= 1e-9 * img.T.size
+        assert np.all(s1 >= 0)
+        total += s1
+    both = prune.spatial_score(sc.arrays(), views, st)
+    assert np.allclose(both, total, rtol=0, atol=1e-12)
+
+
+def test_temporal_second_derivative_and_variation_bounds():
+    """Eq. 5 against central differences of p(t); each Eq. 6 term lies in
+    [1, 2]: 2 where p'' vanishes (long-lived, or far from mu_t), near 1 at
+    mu_t of a short-lived Gaussian (|p''| = 1/Sigma_t large)."""
+    mu = np.array([0.3, 0.5, 0.7])
+    s44 = np.array([1e-4, 0.02, 1e4])
+    p = lambda t: np.exp(-(t - mu) ** 2 / (2 * s44))
+    h = 1e-6
+    for t in (0.29, 0.31, 0.5, 0.9):
+        fd = (p(t + h) - 2 * p(t) + p(t - h)) / h ** 2
+        an = prune.temporal_second_derivative(t, mu, s44)
+        assert np.allclose(an, fd, rtol=2e-3, atol=1e-3 * np.abs(an).max()), (t, an, fd)
+    times = inputs.frame_times(300)
+    tv = prune.temporal_variation_score(mu, s44, times)
+    assert np.all(tv >= len(times) - 1e-9) and np.all(tv <= 2 * len(times) + 1e-9)
+    assert tv[2] > 2 * len(times) - 0.1                      # long lifespan: |p''| <= 1e-4
+    one = prune.temporal_variation_score(np.array([0.5]), np.array([1e-4]), [0.5])
+    assert abs(one[0] - 1.0) < 1e-12                          # tanh(1e4) = 1
+    assert tv[0] < tv[2] and tv[1] < tv[2]
+
+
+def test_volume_weight_and_prune_selection():
+    rng = np.random.default_rng(3)
+    ls = rng.normal(-4, 0.5, (1000, 4))
+    valid = np.ones(1000, dtype=bool)
+    valid[:7] = False
+    g = prune.volume_weight(ls, valid)
+    vol = np.exp(ls.sum(axis=1))
+    top = np.argsort(np.where(valid, vol, 0.0))[int(np.floor(0.9 * 999)):]
+    assert np.all(g[top] == 1.0) and np.all(g[:7] == 0.0)
+    order = np.argsort(vol[valid])
+    assert np.all(np.diff(g[valid][order]) >= 0)              # monotone in the volume
+    vq = np.sort(np.where(valid, vol, 0.0))[int(np.floor(0.9 * 999))]
+    k = np.flatnonzero(valid & (vol < vq))[0]
+    assert abs(g[k] - (vol[k] / vq) ** 0.1) < 1e-12
+    # prune: brute force with ties
+    score = rng.integers(0, 50, 300).astype(float)
+    for keep in (0, 1, 37, 150, 300):
+        got = prune.prune(score, keep)
+        cand = sorted(range(300), key=lambda i: (-score[i], i))[:keep]
+        assert np.array_equal(got, np.sort(np.array(cand, dtype=np.uint32)))
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient the bias-corrected moments are exactly g and
+    g^2 at every step, so each step moves p by lr g / (|g| + eps); entries
+    with zero gradient and zero state never move."""
+    g = np.array([3.0, -0.5, 0.0, 1e-3])
+    for steps in (1, 2, 5):
+        p, m, v = optim.adam([1.0, 1.0, 1.0, 1.0], [g] * steps, lr=0.1, eps=1e-8)
+        assert np.allclose(p, 1.0 - steps * 0.1 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+        assert p[2] == 1.0 and m[2] == 0.0 and v[2] == 0.0
+        assert np.allclose(m, g * (1 - 0.9 ** steps)) and np.allclose(v, g * g * (1 - 0.999 ** steps))
 
 
 # P-14 gradients ------------------------------------------------------------------------------
