@@ -45,7 +45,8 @@ __global__ void __launch_bounds__(kBlock) adam_kernel(AdamArgs a) {
         *reinterpret_cast<float4 *>(a.m + i4) = m;
         *reinterpret_cast<float4 *>(a.v + i4) = v;
     } else {
-        for (int64_t i = i4; i < a.n; ++i) adam_one(a.p[i], a.g[i], a.m[i], a.v[i], a);
+        const int64_t end = min(i4 + 4, a.n);
+        for (int64_t i = i4; i < end; ++i) adam_one(a.p[i], a.g[i], a.m[i], a.v[i], a);
     }
 }
 

@@ -208,21 +208,24 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
     }
 }
 
-// Tile-key emission.  Block b owns the visible Gaussians at sorted positions
-// [256 b, 256 b + 256) and therefore the instances [off[256 b],
-// off[256 b + 256]).  Their tile rows (every row of each rectangle, Gaussian
-// by Gaussian) are processed 256 at a time: a thread finds its row's Gaussian
-// by a binary search over the rows' prefix in LDS and evaluates the row's
-// tile columns (the evaluation the per-Gaussian count used); a block scan of
-// the row counts places the rows' instances, which are contiguous.  The
-// block then writes those instances with consecutive threads (runs of
-// kDupRun, one binary search over the rows per run), so the stores are
-// coalesced however the rows' lengths vary.  Counts and emission use the same
-// float arithmetic, so each Gaussian fills exactly its slots; a tile's column
-// is clamped into its row's span and writes into [first, last), so keys, ids
-// and addresses stay in range whatever the counts hold.
+// Tile-key emission, balanced by instance.  Block b writes the instances
+// [b E, (b + 1) E) (E = kDupE), whatever Gaussians they belong to: in depth
+// order the nearest, largest footprints come first, so a partition by
+// Gaussian would give a few blocks most of the work.  The block finds the
+// Gaussian holding its first instance with a 256-ary search of the offsets,
+// then walks the Gaussians from there, 256 at a time, until one starts past
+// its window.  Their tile rows (every row of each rectangle) are processed 256
+// at a time: a thread finds its row's Gaussian by a binary search over the
+// rows' prefix in LDS and evaluates the row's tile columns (the evaluation the
+// per-Gaussian count used); a block scan of the row counts places the rows'
+// instances, which are contiguous, and each thread writes the part of its row
+// inside the window to an LDS image of the window.  The window then leaves
+// the block as coalesced stores.  Counts and emission use the same float
+// arithmetic, so each Gaussian fills exactly its slots; the LDS image is
+// pre-filled with a valid (key, id) so that every slot holds one whatever the
+// counts hold.
 constexpr int kDupNT = 256;
-constexpr int kDupRun = 8;
+constexpr int kDupE = 2048;
 
 __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order, const uint64_t *offsets,
                                                            const int32_t *rect, const Rec2D *rec,
@@ -233,85 +236,99 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
     __shared__ int4 s_rect[kDupNT];
     __shared__ CullEllipse s_ell[kDupNT];
     __shared__ uint32_t s_id[kDupNT], s_base[kDupNT];
-    __shared__ uint32_t s_rbase[kDupNT + 1];     // first row of each Gaussian in the block's row list
-    __shared__ uint32_t s_rpos[kDupNT + 1];      // per row of the chunk: first instance (block-relative)
-    __shared__ uint32_t s_rkey[kDupNT];          // per row: key of its first tile
-    __shared__ uint32_t s_rlen[kDupNT];          // per row: tiles in the row minus one
-    __shared__ uint32_t s_rid[kDupNT];           // per row: Gaussian position
+    __shared__ uint32_t s_rbase[kDupNT + 1];     // first row of each Gaussian in the batch's row list
+    __shared__ uint32_t s_key[kDupE], s_val[kDupE];
     __shared__ uint32_t s_tmp[kDupNT / 64 + 1];
     const int64_t n_vis = count_of(n_vis_dev, n_max);
-    const int64_t n_inst = *n_inst_dev;
-    const int64_t j0 = (int64_t)blockIdx.x * kDupNT;
-    if (j0 >= n_vis) return;                           // uniform
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n_inst > capacity) atomicOr(overflow, 1);
-    const int cnt = (int)min((int64_t)kDupNT, n_vis - j0);
+    const int64_t n_inst_all = *n_inst_dev;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_inst_all > capacity) atomicOr(overflow, 1);
+    const int64_t n_inst = min(n_inst_all, capacity);
+    const int64_t e_lo = (int64_t)blockIdx.x * kDupE;
+    if (e_lo >= n_inst || n_vis <= 0) return;          // uniform
+    const int64_t e_hi = min(e_lo + (int64_t)kDupE, n_inst);
     const int t = threadIdx.x;
-    uint32_t nrows = 0;
-    if (t < cnt) {
-        const uint32_t id = order[j0 + t];
-        const int4 r = reinterpret_cast<const int4 *>(rect)[id];
-        s_rect[t] = r;
-        s_ell[t] = cull_ellipse(rec[id], rp);
-        s_id[t] = id;
-        // tile keys of view v start at v * tiles per view
-        s_base[t] = view_of ? view_of[id] * (uint32_t)(rp.tiles_x * rp.tiles_y) : 0u;
-        nrows = (uint32_t)(r.w / rp.tile_h - r.y / rp.tile_h + 1);
+
+    // largest g < n_vis with offsets[g] <= e_lo: probes at lo + t * step, the
+    // predicate holds on a prefix of them
+    int64_t lo = 0, hi = n_vis;
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + kDupNT - 1) / kDupNT;
+        const int64_t p = lo + (int64_t)t * step;
+        const uint32_t pr = (p < hi && offsets[p] <= (uint64_t)e_lo) ? 1u : 0u;
+        uint32_t c;
+        block_exclusive_sum<kDupNT>(pr, s_tmp, &c);     // c >= 1: offsets[lo] <= e_lo
+        const int64_t nlo = lo + (int64_t)(c > 1u ? c - 1u : 0u) * step;
+        hi = min(nlo + step, hi);
+        lo = nlo;
     }
-    uint32_t n_rows_total;
-    s_rbase[t] = block_exclusive_sum<kDupNT>(nrows, s_tmp, &n_rows_total);
-    if (t == 0) s_rbase[kDupNT] = n_rows_total;
-    const uint64_t first = offsets[j0];
-    const uint64_t end_g = (j0 + cnt < n_vis) ? offsets[j0 + cnt] : (uint64_t)n_inst;
-    const uint64_t last = min(end_g, (uint64_t)capacity);
+    const uint32_t fill_id = order[lo];
+    for (int i = t; i < kDupE; i += kDupNT) {
+        s_key[i] = 0u;
+        s_val[i] = fill_id;
+    }
+    uint64_t carry = offsets[lo];                      // first instance of the batch's first row
+    bool done = false;
+    for (int64_t g0 = lo; g0 < n_vis && !done; g0 += kDupNT) {
+        const int64_t g = g0 + t;
+        // rows in the low 20 bits, Gaussians starting before e_hi above them
+        uint32_t packed = 0;
+        if (g < n_vis && offsets[g] < (uint64_t)e_hi) {
+            const uint32_t id = order[g];
+            const int4 r = reinterpret_cast<const int4 *>(rect)[id];
+            s_rect[t] = r;
+            s_ell[t] = cull_ellipse(rec[id], rp);
+            s_id[t] = id;
+            // tile keys of view v start at v * tiles per view
+            s_base[t] = view_of ? view_of[id] * (uint32_t)(rp.tiles_x * rp.tiles_y) : 0u;
+            packed = (1u << 20) | (uint32_t)(r.w / rp.tile_h - r.y / rp.tile_h + 1);
+        }
+        uint32_t tot;
+        s_rbase[t] = block_exclusive_sum<kDupNT>(packed, s_tmp, &tot) & 0xfffffu;
+        const uint32_t n_rows_total = tot & 0xfffffu;
+        const int cnt = (int)(tot >> 20);
+        if (t == 0) s_rbase[kDupNT] = n_rows_total;
+        __syncthreads();
+        for (uint32_t row0 = 0; row0 < n_rows_total; row0 += kDupNT) {
+            const uint32_t rho = row0 + (uint32_t)t;
+            uint32_t n = 0, key0 = 0, rid = 0;
+            if (rho < n_rows_total) {
+                int a = 0, b = cnt - 1;                // largest Gaussian with s_rbase <= rho
+                while (a < b) {
+                    const int mid = (a + b + 1) >> 1;
+                    if (s_rbase[mid] <= rho) a = mid; else b = mid - 1;
+                }
+                const int4 r = s_rect[a];
+                const int ty = r.y / rp.tile_h + (int)(rho - s_rbase[a]);
+                int c0, c1;
+                if (tile_row_span(s_ell[a], r, ty, rp.tile_w, rp.tile_h, &c0, &c1)) {
+                    n = (uint32_t)(c1 - c0 + 1);
+                    key0 = s_base[a] + (uint32_t)(ty * rp.tiles_x + c0);
+                }
+                rid = s_id[a];
+            }
+            uint32_t chunk_total;
+            const uint32_t pos = block_exclusive_sum<kDupNT>(n, s_tmp, &chunk_total);
+            // this row holds the instances [carry + pos, carry + pos + n)
+            const int64_t r0 = (int64_t)carry + pos;
+            const int64_t ka = max(r0, e_lo), kb = min(r0 + (int64_t)n, e_hi);
+            for (int64_t k = ka; k < kb; ++k) {
+                s_key[k - e_lo] = key0 + (uint32_t)(k - r0);
+                s_val[k - e_lo] = rid;
+            }
+            carry += chunk_total;
+            if (carry >= (uint64_t)e_hi) {               // uniform: the window is full
+                done = true;
+                break;
+            }
+        }
+        if (cnt < kDupNT) done = true;
+        __syncthreads();                                 // the batch's LDS rows are reused
+    }
     __syncthreads();
-    uint64_t carry = first;
-    for (uint32_t row0 = 0; row0 < n_rows_total; row0 += kDupNT) {
-        const uint32_t rho = row0 + (uint32_t)t;
-        uint32_t n = 0, key0 = 0, rid = 0;
-        if (rho < n_rows_total) {
-            int lo = 0, hi = cnt - 1;                  // largest g with s_rbase[g] <= rho
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_rbase[mid] <= rho) lo = mid; else hi = mid - 1;
-            }
-            const int g = lo;
-            const int4 r = s_rect[g];
-            const int ty = r.y / rp.tile_h + (int)(rho - s_rbase[g]);
-            int c0, c1;
-            if (tile_row_span(s_ell[g], r, ty, rp.tile_w, rp.tile_h, &c0, &c1)) {
-                n = (uint32_t)(c1 - c0 + 1);
-                key0 = s_base[g] + (uint32_t)(ty * rp.tiles_x + c0);
-            }
-            rid = s_id[g];
-        }
-        uint32_t chunk_total;
-        const uint32_t pos = block_exclusive_sum<kDupNT>(n, s_tmp, &chunk_total);
-        s_rpos[t] = pos;
-        s_rkey[t] = key0;
-        s_rlen[t] = n ? n - 1u : 0u;
-        s_rid[t] = rid;
-        if (t == 0) s_rpos[kDupNT] = chunk_total;
-        __syncthreads();
-        // instances [carry, carry + chunk_total): run e0 starts in the last row whose first instance is <= e0
-        const uint64_t stop = min(carry + chunk_total, last);
-        for (uint64_t e0 = carry + (uint64_t)t * kDupRun; e0 < stop; e0 += (uint64_t)kDupNT * kDupRun) {
-            const uint32_t k0 = (uint32_t)(e0 - carry);
-            int lo = 0, hi = kDupNT - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_rpos[mid] <= k0) lo = mid; else hi = mid - 1;
-            }
-            const uint64_t e1 = min(e0 + kDupRun, stop);
-            for (uint64_t e = e0; e < e1; ++e) {
-                const uint32_t k = (uint32_t)(e - carry);
-                while (k >= s_rpos[lo + 1]) ++lo;     // s_rpos[kDupNT] = chunk_total > k ends this
-                // the column offset is clamped to the row's span (a no-op when counts agree)
-                tile_keys[e] = s_rkey[lo] + min(k - s_rpos[lo], s_rlen[lo]);
-                ids[e] = s_rid[lo];
-            }
-        }
-        carry += chunk_total;
-        __syncthreads();
+    const int len = (int)(e_hi - e_lo);
+    for (int i = t; i < len; i += kDupNT) {
+        tile_keys[e_lo + i] = s_key[i];
+        ids[e_lo + i] = s_val[i];
     }
 }
 
@@ -435,7 +452,7 @@ hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, cons
                             const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,
                             const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, hipStream_t s) {
     if (n_max == 0) return hipSuccess;
-    hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_for(n_max, kDupNT)), dim3(kDupNT), 0, s, order, offsets,
+    hipLaunchKernelGGL(duplicate_kernel, dim3(std::max(1u, blocks_for(capacity, kDupE))), dim3(kDupNT), 0, s, order, offsets,
                        rect, rec, view_of, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
     return hipGetLastError();
 }

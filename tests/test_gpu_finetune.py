@@ -37,7 +37,10 @@ def test_adam_kernel_matches_oracle(ctx, n, offset):
                                           ctypes.c_float(0.9), ctypes.c_float(0.999), ctypes.c_float(1e-8), t,
                                           _stream(0)))
     torch.cuda.synchronize()
-    ref, rm, rv = optim.adam(p0[offset:], [g[offset:] for g in grads], lr=1e-2, eps=1e-8)
+    # the entry point takes float32 hyperparameters: the oracle gets the same values
+    f32 = lambda x: float(np.float32(x))
+    ref, rm, rv = optim.adam(p0[offset:], [g[offset:] for g in grads], lr=f32(1e-2), b1=f32(0.9), b2=f32(0.999),
+                             eps=f32(1e-8))
     got = p.cpu().numpy()
     assert np.array_equal(got[:offset], p0[:offset])
     assert np.allclose(got[offset:], ref, rtol=0, atol=2e-6 * (1 + np.abs(ref).max()))
