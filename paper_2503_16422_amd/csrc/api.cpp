@@ -72,6 +72,7 @@ void release(Buf &b) {
 }
 
 constexpr int32_t kDefaultPpt = 2;
+constexpr int64_t kBucketMaxN = int64_t(1) << 20;   // largest processed count ordered by buckets
 
 bool valid_tile(int w, int h) { return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8); }
 
@@ -88,6 +89,7 @@ struct fdgs_state {
     bool has_forward = false;
     // per processed Gaussian
     Buf rec, depth_key, rect, tiles, visible, vis_pos, order_k, order_v, order_k2, order_v2, offsets, view_of;
+    Buf bucket;        // depth buckets: counts, cursors, starts, key range
     // per instance
     Buf tkeys, tids, tkeys2, tids2;
     // per tile / pixel
@@ -113,8 +115,8 @@ struct fdgs_state {
 
     void free_all() {
         for (Buf *b : {&rec, &depth_key, &rect, &tiles, &visible, &vis_pos, &order_k, &order_v, &order_k2,
-                       &order_v2, &offsets, &view_of, &tkeys, &tids, &tkeys2, &tids2, &ranges, &sched, &T_final,
-                       &n_contrib, &counts, &g2d, &scratch})
+                       &order_v2, &offsets, &view_of, &bucket, &tkeys, &tids, &tkeys2, &tids2, &ranges, &sched,
+                       &T_final, &n_contrib, &counts, &g2d, &scratch})
             release(*b);
     }
 };
@@ -517,6 +519,11 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     HIP_TRY(ensure(S->order_v2, sizeof(uint32_t) * n_max));
     HIP_TRY(ensure(S->offsets, sizeof(uint64_t) * n_max));
     if (V > 1) HIP_TRY(ensure(S->view_of, sizeof(uint32_t) * n_max));
+    // one view of at most kBucketMaxN processed Gaussians: depth order by buckets (three launches)
+    const bool by_buckets = V == 1 && n_max <= kBucketMaxN;
+    const int64_t n_buckets = int64_t(1) << bucket_log2_for(n_max);
+    if (by_buckets) HIP_TRY(ensure(S->bucket, sizeof(uint32_t) * bucket_scratch_words(n_max)));
+    uint32_t *bwork = by_buckets ? S->bucket.as<uint32_t>() : nullptr;
     HIP_TRY(ensure(S->counts, sizeof(int64_t) * 4));
     HIP_TRY(ensure(S->ranges, sizeof(uint32_t) * 2 * n_keys));
     if (cfg->schedule) HIP_TRY(ensure(S->sched, sizeof(uint32_t) * (n_keys + 1)));
@@ -540,27 +547,35 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
         if (need_state) HIP_TRY(ensure(S->vis_pos, sizeof(uint32_t) * n_max));
         HIP_TRY(compact_visible(S->visible.as<uint8_t>(), S->depth_key.as<uint64_t>(), n_dev, n_max, counts + 0,
                                 S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(),
-                                need_state ? S->vis_pos.as<uint32_t>() : nullptr, S->scratch.p, stream));
+                                need_state ? S->vis_pos.as<uint32_t>() : nullptr, bwork, by_buckets ? 2 * n_buckets : 0,
+                                by_buckets ? bwork + 3 * n_buckets + 1 : nullptr, S->scratch.p, stream));
     }
     uint32_t *ov = nullptr;
     {
         StageTimer tm(ctx, FDGS_STAGE_DEPTH_SORT, stream);
-        int alt = 0;
-        HIP_TRY(radix_sort_u32(S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->order_k2.as<uint32_t>(),
-                               S->order_v2.as<uint32_t>(), counts + 0, n_max, 0, 32, S->scratch.p, &alt, stream));
-        uint32_t *ok = alt ? S->order_k2.as<uint32_t>() : S->order_k.as<uint32_t>();
-        ov = alt ? S->order_v2.as<uint32_t>() : S->order_v.as<uint32_t>();
-        HIP_TRY(launch_fix_depth_ties(ok, ov, S->depth_key.as<uint64_t>(), counts + 0, n_max,
-                                      ctx->overflow.as<int32_t>(), stream));
-        if (V > 1) {
-            // group by view, keeping the depth order inside each view (stable)
-            uint32_t *kv = alt ? S->order_k.as<uint32_t>() : S->order_k2.as<uint32_t>();
-            uint32_t *vv = alt ? S->order_v.as<uint32_t>() : S->order_v2.as<uint32_t>();
-            HIP_TRY(launch_gather_u32(view_of, ov, ok, counts + 0, n_max, stream));
-            int alt_v = 0;
-            HIP_TRY(radix_sort_u32(ok, ov, kv, vv, counts + 0, n_max, 0, std::max(1, bits_for(V)), S->scratch.p,
-                                   &alt_v, stream));
-            if (alt_v) ov = vv;
+        if (by_buckets) {
+            ov = S->order_v2.as<uint32_t>();
+            HIP_TRY(depth_order_buckets(S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), counts + 0, n_max,
+                                        S->depth_key.as<uint64_t>(), bwork, S->order_v.as<uint32_t>(),
+                                        S->order_k2.as<uint32_t>(), ov, stream));
+        } else {
+            int alt = 0;
+            HIP_TRY(radix_sort_u32(S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(), S->order_k2.as<uint32_t>(),
+                                   S->order_v2.as<uint32_t>(), counts + 0, n_max, 0, 32, S->scratch.p, &alt, stream));
+            uint32_t *ok = alt ? S->order_k2.as<uint32_t>() : S->order_k.as<uint32_t>();
+            ov = alt ? S->order_v2.as<uint32_t>() : S->order_v.as<uint32_t>();
+            HIP_TRY(launch_fix_depth_ties(ok, ov, S->depth_key.as<uint64_t>(), counts + 0, n_max,
+                                          ctx->overflow.as<int32_t>(), stream));
+            if (V > 1) {
+                // group by view, keeping the depth order inside each view (stable)
+                uint32_t *kv = alt ? S->order_k.as<uint32_t>() : S->order_k2.as<uint32_t>();
+                uint32_t *vv = alt ? S->order_v.as<uint32_t>() : S->order_v2.as<uint32_t>();
+                HIP_TRY(launch_gather_u32(view_of, ov, ok, counts + 0, n_max, stream));
+                int alt_v = 0;
+                HIP_TRY(radix_sort_u32(ok, ov, kv, vv, counts + 0, n_max, 0, std::max(1, bits_for(V)), S->scratch.p,
+                                       &alt_v, stream));
+                if (alt_v) ov = vv;
+            }
         }
     }
     S->vis_list = need_state ? S->vis_pos.as<uint32_t>() : nullptr;

@@ -58,10 +58,23 @@ hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t 
                            const int64_t *n_dev, int64_t n_max, int64_t *total,
                            void *scratch, hipStream_t s);
 // Visible entries in order -> keys32 = float32 bits of their depth, vals = position (and, when asc is
-// not NULL, asc = position too: a copy the depth sort does not overwrite); *total = count.
+// not NULL, asc = position too: a copy the depth sort does not overwrite); *total = count.  Before the
+// entries are written, clear[0..n_clear) is zeroed and range (when not NULL) receives the [min, max]
+// of the keys.
 hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
-                           int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, void *scratch,
-                           hipStream_t s);
+                           int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, uint32_t *clear,
+                           int64_t n_clear, uint32_t *range, void *scratch, hipStream_t s);
+
+// Depth order of one view's visible entries by bucketing and per-bucket sorts: out[0..n_vis) = the
+// positions (vals) ordered by (depth_key[pos], pos).  work holds bucket_scratch_words(n_max) words:
+// counts and cursors (words [0, 2 nb), cleared by compact_visible), bucket starts, and the key range
+// (words 3 nb + 1 and 3 nb + 2, filled by compact_visible).  bucketed and alt are scratch of n_max
+// words; none of the arrays may alias.
+int bucket_log2_for(int64_t n_max);
+size_t bucket_scratch_words(int64_t n_max);
+hipError_t depth_order_buckets(const uint32_t *keys32, const uint32_t *vals, const int64_t *n_vis_dev, int64_t n_max,
+                               const uint64_t *depth_key, uint32_t *work, uint32_t *alt, uint32_t *bucketed,
+                               uint32_t *out, hipStream_t s);
 hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t *count,
                         void *scratch, hipStream_t s);
 size_t compact_scratch_bytes(int64_t n);

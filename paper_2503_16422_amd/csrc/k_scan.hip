@@ -18,18 +18,54 @@ __device__ __forceinline__ int64_t count_of(const int64_t *n_dev, int64_t n_max)
 }
 
 // Loader for the scanned value of element j: flags (u8) or u32 counts,
-// optionally read through a gather index.
+// optionally read through a gather index.  A thread whose first element lies
+// past the count loads nothing; otherwise its element indices are clamped to
+// the last counted element (so a gather only follows indices that were
+// written) and the values past the count are masked to zero afterwards.  The
+// loads of all items then carry no branch and are issued together (a gather
+// issues its index loads, then its value loads).
 struct LoadU8 {
     const uint8_t *in;
-    __device__ __forceinline__ uint64_t operator()(int64_t j) const { return in[j]; }
+    template <int K>
+    __device__ __forceinline__ void load(const int64_t (&j)[K], uint64_t (&v)[K]) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = in[j[k]];
+    }
 };
 struct LoadU32 {
     const uint32_t *in;
     const uint32_t *gather;
-    __device__ __forceinline__ uint64_t operator()(int64_t j) const {
-        return in[gather ? (int64_t)gather[j] : j];
+    template <int K>
+    __device__ __forceinline__ void load(const int64_t (&j)[K], uint64_t (&v)[K]) const {
+        if (gather) {
+            uint32_t g[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) g[k] = gather[j[k]];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = in[g[k]];
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = in[j[k]];
+        }
     }
 };
+
+// The thread's kItems consecutive elements starting at base, zero past n.
+template <typename Load>
+__device__ __forceinline__ void load_items(const Load &ld, int64_t base, int64_t n, uint64_t (&v)[kItems]) {
+    if (base >= n) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) v[k] = 0;
+        return;
+    }
+    int64_t j[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) j[k] = min(base + k, n - 1);
+    ld.load(j, v);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        if (base + k >= n) v[k] = 0;
+}
 
 template <typename Load>
 __global__ void __launch_bounds__(kNT) reduce_kernel(Load ld, const int64_t *n_dev, int64_t n_max,
@@ -37,19 +73,27 @@ __global__ void __launch_bounds__(kNT) reduce_kernel(Load ld, const int64_t *n_d
     __shared__ uint64_t tmp[kNT / 64 + 1];
     const int64_t n = count_of(n_dev, n_max);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+    uint64_t v[kItems];
+    load_items(ld, base, n, v);
     uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k)
-        if (base + k < n) s += ld(base + k);
+    for (int k = 0; k < kItems; ++k) s += v[k];
     uint64_t total;
     block_exclusive_sum<kNT>(s, tmp, &total);
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
 // Exclusive scan of nb block sums by one block; writes the grand total.
-__global__ void __launch_bounds__(kTopNT) top_scan_kernel(uint64_t *partial, int64_t nb,
-                                                          int64_t *total) {
+// Optionally clears n_clear words and resets a [min, max] key range to
+// (all ones, 0) for the kernel that follows.
+__global__ void __launch_bounds__(kTopNT) top_scan_kernel(uint64_t *partial, int64_t nb, int64_t *total,
+                                                          uint32_t *clear, int64_t n_clear, uint32_t *range) {
     __shared__ uint64_t tmp[kTopNT / 64 + 1];
+    for (int64_t i = threadIdx.x; i < n_clear; i += kTopNT) clear[i] = 0u;
+    if (range && threadIdx.x == 0) {
+        range[0] = ~0u;
+        range[1] = 0u;
+    }
     uint64_t carry = 0;
     for (int64_t start = 0; start < nb; start += kTopNT) {
         const int64_t j = start + threadIdx.x;
@@ -69,12 +113,10 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(Load ld, const int64_t *
     const int64_t n = count_of(n_dev, n_max);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
     uint64_t v[kItems];
+    load_items(ld, base, n, v);
     uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        v[k] = base + k < n ? ld(base + k) : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < kItems; ++k) s += v[k];
     uint64_t total;
     uint64_t run = block_exclusive_sum<kNT>(s, tmp, &total) + partial[blockIdx.x];
 #pragma unroll
@@ -91,22 +133,26 @@ hipError_t scan_impl(Load ld, Out *out, const int64_t *n_dev, int64_t n_max, int
     uint64_t *partial = static_cast<uint64_t *>(scratch);
     if (nb == 0) {
         // still define the total
-        hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, (int64_t)0, total);
+        hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, (int64_t)0, total,
+                           (uint32_t *)nullptr, (int64_t)0, (uint32_t *)nullptr);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((reduce_kernel<Load>), dim3((unsigned)nb), dim3(kNT), 0, s, ld, n_dev, n_max, partial);
-    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total);
+    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total, (uint32_t *)nullptr,
+                       (int64_t)0, (uint32_t *)nullptr);
     hipLaunchKernelGGL((downsweep_kernel<Load, Out>), dim3((unsigned)nb), dim3(kNT), 0, s, ld, n_dev,
                        n_max, (const uint64_t *)partial, out);
     return hipGetLastError();
 }
 
 // Visible compaction: the downsweep of a scan over the visible flags that
-// writes each visible entry's (float32 depth bits, position) to its slot.
+// writes each visible entry's (float32 depth bits, position) to its slot and,
+// when range is given, folds the keys into range = [min, max] (positive
+// floats: bit order is value order).
 __global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *visible, const uint64_t *depth_key,
                                                               const int64_t *n_dev, int64_t n_max,
                                                               const uint64_t *partial, uint32_t *keys32,
-                                                              uint32_t *vals, uint32_t *asc) {
+                                                              uint32_t *vals, uint32_t *asc, uint32_t *range) {
     __shared__ uint64_t tmp[kNT / 64 + 1];
     const int64_t n = count_of(n_dev, n_max);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
@@ -119,14 +165,43 @@ __global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *vis
     }
     uint64_t total;
     uint64_t run = block_exclusive_sum<kNT>(s, tmp, &total) + partial[blockIdx.x];
+    uint32_t kmin = ~0u, kmax = 0u;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         if (v[k]) {
             const double z = __longlong_as_double((long long)depth_key[base + k]);
-            keys32[run] = __float_as_uint((float)z);   // z > 0: bit order = value order
+            const uint32_t key = __float_as_uint((float)z);   // z > 0: bit order = value order
+            keys32[run] = key;
             vals[run] = (uint32_t)(base + k);
             if (asc) asc[run] = (uint32_t)(base + k);
+            kmin = min(kmin, key);
+            kmax = max(kmax, key);
             ++run;
+        }
+    }
+    if (range) {
+        // block minimum and maximum, then one atomic pair per block
+        __shared__ uint32_t s_min[kNT / 64], s_max[kNT / 64];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
+        }
+        if (lane_id() == 0) {
+            s_min[wave_id()] = kmin;
+            s_max[wave_id()] = kmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 1; w < kNT / 64; ++w) {
+                kmin = min(kmin, s_min[w]);
+                kmax = max(kmax, s_max[w]);
+            }
+            if (kmin <= kmax) {
+                atomicMin(&range[0], kmin);
+                atomicMax(&range[1], kmax);
+            }
         }
     }
 }
@@ -195,17 +270,17 @@ hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t 
 }
 
 hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
-                           int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, void *scratch,
-                           hipStream_t s) {
+                           int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, uint32_t *clear,
+                           int64_t n_clear, uint32_t *range, void *scratch, hipStream_t s) {
     const int64_t nb = (n_max + kChunk - 1) / kChunk;
     uint64_t *partial = static_cast<uint64_t *>(scratch);
     if (nb > 0)
         hipLaunchKernelGGL((reduce_kernel<LoadU8>), dim3((unsigned)nb), dim3(kNT), 0, s, LoadU8{visible}, n_dev, n_max,
                            partial);
-    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total);
+    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total, clear, n_clear, range);
     if (nb > 0)
         hipLaunchKernelGGL(compact_visible_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, visible, depth_key, n_dev,
-                           n_max, (const uint64_t *)partial, keys32, vals, asc);
+                           n_max, (const uint64_t *)partial, keys32, vals, asc, range);
     return hipGetLastError();
 }
 
@@ -216,7 +291,8 @@ hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t 
     const int64_t nw = (n + 31) / 32;
     if (nb > 0)
         hipLaunchKernelGGL(bits_count_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, nw, partial);
-    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, count);
+    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, count, (uint32_t *)nullptr,
+                       (int64_t)0, (uint32_t *)nullptr);
     if (nb > 0)
         hipLaunchKernelGGL(bits_compact_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, n,
                            (const uint64_t *)partial, idx);

@@ -30,21 +30,49 @@ __device__ __forceinline__ int64_t count_of(const int64_t *n_dev, int64_t n_max)
     return n_dev ? min(*n_dev, n_max) : n_max;
 }
 
+// Lanes of the wave whose `bits`-bit digit equals this lane's, among the
+// lanes where `valid` holds: one ballot per digit bit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, bool valid) {
+    uint64_t match = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        match &= bit ? bb : ~bb;
+    }
+    return match;
+}
+
 // Per-block digit histogram, stored digit-major: hist[d * nb + b].  Block b
-// owns keys [b * KPT * kNT, (b + 1) * KPT * kNT).
+// owns keys [b * KPT * kNT, (b + 1) * KPT * kNT).  All loads are issued
+// before the first use (indices clamped to the last counted key, so no branch
+// separates them), and each wave adds one count per distinct digit of a
+// round: skewed digits (the exponent byte of depths, the high bits of tile
+// ids) do not serialise on one LDS address.
 template <int KPT>
 __global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, const int64_t *n_dev,
-                                                      int64_t n_max, int shift, uint32_t mask,
-                                                      uint32_t *hist) {
+                                                      int64_t n_max, int shift, int bits, uint32_t *hist) {
     __shared__ uint32_t h[kRadix];
     const int64_t n = count_of(n_dev, n_max);
+    const uint32_t mask = (1u << bits) - 1u;
     h[threadIdx.x] = 0;
+    const int64_t base = (int64_t)blockIdx.x * (KPT * kNT) + (int64_t)wave_id() * (KPT * 64) + lane_id();
+    uint32_t k[KPT];
+    if (base < n) {
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) k[r] = keys[min(base + (int64_t)r * 64, n - 1)];
+    } else {
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) k[r] = 0u;
+    }
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * (KPT * kNT);
+    const uint64_t lt_mask = (lane_id() == 0) ? 0ull : ((~0ull) >> (64 - lane_id()));
 #pragma unroll
     for (int r = 0; r < KPT; ++r) {
-        const int64_t j = base + (int64_t)r * kNT + threadIdx.x;
-        if (j < n) atomicAdd(&h[(keys[j] >> shift) & mask], 1u);
+        const bool valid = base + (int64_t)r * 64 < n;
+        const uint32_t d = (k[r] >> shift) & mask;
+        const uint64_t match = match_digit(d, bits, valid);
+        const uint32_t cnt = __popcll(match);
+        if (valid && __popcll(match & lt_mask) == cnt - 1) atomicAdd(&h[d], cnt);   // last lane of its group
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -99,19 +127,24 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
     const int64_t bbase = (int64_t)blockIdx.x * CH;
     const int64_t wbase = bbase + (int64_t)w * (KPT * 64);
     uint32_t key[KPT], val[KPT], rank[KPT];
+    // every load first (indices clamped to the last counted key), so that
+    // the wave waits for memory once rather than once per round
+    if (wbase + lane < n) {
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int64_t j = min(wbase + (int64_t)r * 64 + lane, n - 1);
+            key[r] = keys[j];
+            val[r] = vals[j];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) key[r] = val[r] = 0u;
+    }
 #pragma unroll
     for (int r = 0; r < KPT; ++r) {
-        const int64_t j = wbase + (int64_t)r * 64 + lane;
-        const bool valid = j < n;
-        key[r] = valid ? keys[j] : 0u;
-        val[r] = valid ? vals[j] : 0u;
+        const bool valid = wbase + (int64_t)r * 64 + lane < n;
         const uint32_t d = (key[r] >> shift) & mask;
-        uint64_t match = __ballot(valid);
-        for (int b = 0; b < bits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            match &= bit ? bb : ~bb;
-        }
+        const uint64_t match = match_digit(d, bits, valid);
         const uint32_t before = __popcll(match & lt_mask);
         const uint32_t cnt = __popcll(match);
         const uint32_t run = valid ? s_cnt[w][d] : 0u;
@@ -350,25 +383,24 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
     if (j < n) p[j] = v;
 }
 
-// Tile ranges by binary search: tile t's list is [lower_bound(t), lower_bound(t + 1))
-// in the sorted keys, so every tile (empty ones too) is written by one thread.
+// Tile ranges from the boundaries of the sorted keys.  Tile t's list is
+// [lower_bound(t), lower_bound(t + 1)).  Thread i in [0, n] looks at the keys
+// on either side of position i (-1 before the first, n_tiles after the
+// last): every tile t with prev < t <= next has lower_bound(t) = i, and every
+// tile with prev <= t < next has lower_bound(t + 1) = i.  Each range entry is
+// written by exactly one thread (empty tiles too), from one streaming read of
+// the keys.
 __global__ void ranges_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max, int32_t n_tiles,
                               uint32_t *ranges) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tiles) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = count_of(n_dev, n_max);
-    auto lower = [&](uint32_t key) {
-        int64_t lo = 0, hi = n;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (keys[mid] < key) lo = mid + 1; else hi = mid;
-        }
-        return lo;
-    };
-    ranges[2 * t] = (uint32_t)lower((uint32_t)t);
-    ranges[2 * t + 1] = (uint32_t)lower((uint32_t)t + 1u);
+    if (i > n) return;
+    const int64_t prev = i == 0 ? -1 : (int64_t)min(keys[i - 1], (uint32_t)n_tiles);
+    const int64_t next = i == n ? (int64_t)n_tiles : (int64_t)min(keys[i], (uint32_t)n_tiles);
+    if (prev == next) return;
+    for (int64_t t = prev + 1; t <= next && t < n_tiles; ++t) ranges[2 * t] = (uint32_t)i;
+    for (int64_t t = max(prev, (int64_t)0); t < next; ++t) ranges[2 * t + 1] = (uint32_t)i;
 }
-
 
 __global__ void accumulate_counts_kernel(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
                                          int64_t capacity, unsigned long long *acc) {
@@ -396,9 +428,8 @@ template <int KPT>
 static void sort_pass(const uint32_t *src_k, const uint32_t *src_v, uint32_t *dst_k, uint32_t *dst_v,
                       const int64_t *n_dev, int64_t n_max, int shift, int bits, uint32_t *hist,
                       uint32_t *digit_total, int64_t nb, hipStream_t s) {
-    const uint32_t mask = (1u << bits) - 1u;
     hipLaunchKernelGGL((upsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, n_dev, n_max, shift,
-                       mask, hist);
+                       bits, hist);
     hipLaunchKernelGGL(rowscan_kernel, dim3(kRadix), dim3(1024), 0, s, hist, nb, digit_total);
     hipLaunchKernelGGL((downsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, src_v, dst_k, dst_v,
                        n_dev, n_max, shift, bits, (const uint32_t *)hist, (const uint32_t *)digit_total);
@@ -487,7 +518,7 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
                               int32_t n_tiles, uint32_t *ranges, hipStream_t s) {
     if (n_tiles > 0)
-        hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n_tiles, 256)), dim3(256), 0, s, tile_keys, n_inst_dev,
+        hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n_max + 1, 256)), dim3(256), 0, s, tile_keys, n_inst_dev,
                            n_max, n_tiles, ranges);
     return hipGetLastError();
 }

@@ -198,6 +198,29 @@ def test_depth_ties_ordered_by_position(ctx):
     ctx.release(st)
 
 
+def test_many_equal_depths_sorted_through_merges(ctx):
+    """5000 of 6000 Gaussians share one exact depth: their depth bucket is
+    larger than one LDS sort, so it is sorted in chunks and merged; the tile
+    lists must still follow (depth, index) exactly."""
+    sc = inputs.tiny_scene(6000, seed=5)
+    sc.mean[:, 500:5500] = sc.mean[:, 500:501]
+    sc.log_scale[:, 500:5500] = sc.log_scale[:, 500:501]
+    sc.q_left[:, 500:5500] = sc.q_left[:, 500:501]
+    sc.q_right[:, 500:5500] = sc.q_right[:, 500:501]
+    sc.opacity_logit[500:5500] = -3.0
+    cam = inputs.look_at_camera(10.0, 3.0, 48, 40)
+    t = float(sc.mean[3, 500])
+    _, _, st = ctx.render(to_dev(sc), cam, t, _lib.default_cfg(tile_cull=0), keep_state=True)
+    b = ctx.binning(st)
+    torch.cuda.synchronize()
+    pre = oc.prepare(sc.arrays(), cam, t, oracle_settings())
+    assert pre.visible[500:5500].all()
+    ids, _, ranges = obin.bin_gaussians(pre.rect, pre.depth, pre.visible, 48, 40, 16, 16)
+    assert np.array_equal(b["sorted_ids"].cpu().numpy().astype(np.uint32), ids)
+    assert_same_ranges(b["tile_ranges"].cpu().numpy().astype(np.uint32), ranges)
+    ctx.release(st)
+
+
 def assert_same_ranges(got, ref):
     """Non-empty tiles must match exactly; an empty tile may be any [s, s)."""
     nonempty = ref[:, 1] > ref[:, 0]
