@@ -596,19 +596,26 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     HIP_TRY(ensure(S->tids, sizeof(uint32_t) * capacity));
     HIP_TRY(ensure(S->tkeys2, sizeof(uint32_t) * capacity));
     HIP_TRY(ensure(S->tids2, sizeof(uint32_t) * capacity));
-    HIP_TRY(ensure(S->scratch, std::max(scratch, sort_scratch_bytes(capacity))));
+    // the duplicate writes the tile sort's first-digit histogram when its windows tile the sort's blocks
+    const int tile_bits = std::max(1, bits_for(n_keys));
+    const int sort_chunk = radix_chunk(capacity);
+    const int64_t hist_cols = (capacity > 0 && sort_chunk % duplicate_window() == 0)
+                                  ? (capacity + sort_chunk - 1) / sort_chunk * (sort_chunk / duplicate_window())
+                                  : 0;
+    HIP_TRY(ensure(S->scratch, std::max(scratch, sort_scratch_bytes(capacity, hist_cols))));
     {
         StageTimer tm(ctx, FDGS_STAGE_DUPLICATE, stream);
         HIP_TRY(launch_duplicate(ov, S->offsets.as<uint64_t>(), S->rect.as<int32_t>(), S->rec.as<Rec2D>(), view_of, counts + 0, n_max, rp,
                                  S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), counts + 1, capacity,
-                                 ctx->overflow.as<int32_t>(), stream));
+                                 ctx->overflow.as<int32_t>(), hist_cols ? S->scratch.as<uint32_t>() : nullptr,
+                                 radix_first_bits(0, tile_bits), hist_cols, stream));
     }
     {
         StageTimer tm(ctx, FDGS_STAGE_TILE_SORT, stream);
         int alt2 = 0;
         HIP_TRY(radix_sort_u32(S->tkeys.as<uint32_t>(), S->tids.as<uint32_t>(), S->tkeys2.as<uint32_t>(),
-                               S->tids2.as<uint32_t>(), counts + 1, capacity, 0, std::max(1, bits_for(n_keys)),
-                               S->scratch.p, &alt2, stream));
+                               S->tids2.as<uint32_t>(), counts + 1, capacity, 0, tile_bits, S->scratch.p, &alt2, stream,
+                               hist_cols));
         S->sorted_keys = alt2 ? S->tkeys2.as<uint32_t>() : S->tkeys.as<uint32_t>();
         S->sorted_ids = alt2 ? S->tids2.as<uint32_t>() : S->tids.as<uint32_t>();
     }

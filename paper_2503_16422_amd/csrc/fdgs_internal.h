@@ -79,11 +79,16 @@ hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t 
                         void *scratch, hipStream_t s);
 size_t compact_scratch_bytes(int64_t n);
 
-// Stable LSD radix sort of (key, uint32 value) pairs, 8-bit digits.
-size_t sort_scratch_bytes(int64_t n_max);
+// Stable LSD radix sort of (key, uint32 value) pairs, digits of at most 8 bits (passes of near-equal
+// width).  Keys [b chunk, (b + 1) chunk) form block b of every pass (chunk = radix_chunk(n_max)).  When
+// first_hist_cols > 0 the first pass's digit histogram (digit-major, first_hist_cols columns, an equal
+// number per block, digit width radix_first_bits) is already at the start of scratch.
+size_t sort_scratch_bytes(int64_t n_max, int64_t hist_cols = 0);
+int radix_chunk(int64_t n_max);
+int radix_first_bits(int begin_bit, int end_bit);
 hipError_t radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                           const int64_t *n_dev, int64_t n_max, int begin_bit, int end_bit,
-                          void *scratch, int *result_in_alt, hipStream_t s);
+                          void *scratch, int *result_in_alt, hipStream_t s, int64_t first_hist_cols = 0);
 
 // Visible-set compaction, depth ordering and tile binning.
 hipError_t launch_scatter_visible(const uint8_t *visible, const uint32_t *pos,
@@ -92,11 +97,15 @@ hipError_t launch_scatter_visible(const uint8_t *visible, const uint32_t *pos,
 // flag |= 2 when a run of equal float32 depths is too long to reorder.
 hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_t *depth_key,
                                  const int64_t *n_vis_dev, int64_t n_max, int32_t *flag, hipStream_t s);
-// Tile key = view * tiles_per_view + ty * tiles_x + tx (view_of null: view 0).
+// Tile key = view * tiles_per_view + ty * tiles_x + tx (view_of null: view 0).  Instances are written
+// in windows of duplicate_window(); with hist, window w also writes hist[d * hist_cols + w] = its count
+// of keys whose low hist_bits bits equal d (d < 256), and the launch has exactly hist_cols windows.
+int duplicate_window();
 hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
                             const Rec2D *rec, const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
                             const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,
-                            const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, hipStream_t s);
+                            const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, uint32_t *hist,
+                            int hist_bits, int64_t hist_cols, hipStream_t s);
 // dst[j] = src[idx[j]] for j < count.
 hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, const int64_t *n_dev,
                              int64_t n_max, hipStream_t s);

@@ -110,6 +110,7 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
                                                         uint32_t *keys_out, uint32_t *vals_out,
                                                         const int64_t *n_dev, int64_t n_max,
                                                         int shift, int bits, const uint32_t *hist,
+                                                        int64_t hist_cols, int hist_ratio,
                                                         const uint32_t *digit_total) {
     constexpr int CH = KPT * kNT;
     __shared__ uint32_t s_cnt[kNW][kRadix];   // per-wave digit counts, then block-local offsets
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
     const int dd = threadIdx.x;                  // thread dd owns digit dd
     uint32_t tot;
     const uint32_t gbase = block_exclusive_sum<kNT>(digit_total[dd], s_tmp, &tot) +
-                           hist[(int64_t)dd * gridDim.x + blockIdx.x];
+                           hist[(int64_t)dd * hist_cols + (int64_t)blockIdx.x * hist_ratio];
     uint32_t dcount = 0;
 #pragma unroll
     for (int k = 0; k < kNW; ++k) dcount += s_cnt[k][dd];
@@ -265,7 +266,8 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
                                                            const uint32_t *view_of, const int64_t *n_vis_dev,
                                                            int64_t n_max, RenderParams rp, uint32_t *tile_keys,
                                                            uint32_t *ids, const int64_t *n_inst_dev,
-                                                           int64_t capacity, int32_t *overflow) {
+                                                           int64_t capacity, int32_t *overflow, uint32_t *hist,
+                                                           int hist_bits) {
     __shared__ int4 s_rect[kDupNT];
     __shared__ CullEllipse s_ell[kDupNT];
     __shared__ uint32_t s_id[kDupNT], s_base[kDupNT];
@@ -277,7 +279,10 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_inst_all > capacity) atomicOr(overflow, 1);
     const int64_t n_inst = min(n_inst_all, capacity);
     const int64_t e_lo = (int64_t)blockIdx.x * kDupE;
-    if (e_lo >= n_inst || n_vis <= 0) return;          // uniform
+    if (e_lo >= n_inst || n_vis <= 0) {                // uniform
+        if (hist) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = 0u;   // empty window
+        return;
+    }
     const int64_t e_hi = min(e_lo + (int64_t)kDupE, n_inst);
     const int t = threadIdx.x;
 
@@ -363,6 +368,17 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
         tile_keys[e_lo + i] = s_key[i];
         ids[e_lo + i] = s_val[i];
     }
+    if (hist) {
+        // the window's counts of the tile sort's first digit, written where
+        // that sort's upsweep would put them (column = window)
+        uint32_t *s_h = s_rbase;                         // kDupNT + 1 >= 256 words, free again
+        s_h[t] = 0u;
+        __syncthreads();
+        const uint32_t dmask = (1u << hist_bits) - 1u;
+        for (int i = t; i < len; i += kDupNT) atomicAdd(&s_h[s_key[i] & dmask], 1u);
+        __syncthreads();
+        hist[(int64_t)t * gridDim.x + blockIdx.x] = s_h[t];
+    }
 }
 
 __global__ void gather_u32_kernel(const uint32_t *src, const uint32_t *idx, uint32_t *dst,
@@ -383,15 +399,16 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
     if (j < n) p[j] = v;
 }
 
-// Tile ranges from the boundaries of the sorted keys.  Tile t's list is
-// [lower_bound(t), lower_bound(t + 1)).  Thread i in [0, n] looks at the keys
-// on either side of position i (-1 before the first, n_tiles after the
-// last): every tile t with prev < t <= next has lower_bound(t) = i, and every
-// tile with prev <= t < next has lower_bound(t + 1) = i.  Each range entry is
-// written by exactly one thread (empty tiles too), from one streaming read of
-// the keys.
-__global__ void ranges_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max, int32_t n_tiles,
-                              uint32_t *ranges) {
+// Tile ranges.  Tile t's list is [lower_bound(t), lower_bound(t + 1)) in the
+// sorted keys.  Two equivalent kernels: with lists of a few hundred entries a
+// thread per position i in [0, n] looks at the keys on either side of i (-1
+// before the first, n_tiles after the last): every tile t with prev < t <=
+// next has lower_bound(t) = i, and every tile with prev <= t < next has
+// lower_bound(t + 1) = i, so each entry is written by exactly one thread from
+// one streaming read of the keys.  With long lists (few tiles, many
+// instances) a thread per tile binary-searches its two bounds instead.
+__global__ void ranges_boundary_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max, int32_t n_tiles,
+                                       uint32_t *ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = count_of(n_dev, n_max);
     if (i > n) return;
@@ -400,6 +417,23 @@ __global__ void ranges_kernel(const uint32_t *keys, const int64_t *n_dev, int64_
     if (prev == next) return;
     for (int64_t t = prev + 1; t <= next && t < n_tiles; ++t) ranges[2 * t] = (uint32_t)i;
     for (int64_t t = max(prev, (int64_t)0); t < next; ++t) ranges[2 * t + 1] = (uint32_t)i;
+}
+
+__global__ void ranges_search_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max, int32_t n_tiles,
+                                     uint32_t *ranges) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t n = count_of(n_dev, n_max);
+    auto lower = [&](uint32_t key) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    ranges[2 * t] = (uint32_t)lower((uint32_t)t);
+    ranges[2 * t + 1] = (uint32_t)lower((uint32_t)t + 1u);
 }
 
 __global__ void accumulate_counts_kernel(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
@@ -413,49 +447,74 @@ __global__ void accumulate_counts_kernel(const int64_t *n_proc_dev, int64_t n_pr
 
 inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
 
+// instances per tile (capacity / tiles) above which ranges come from binary searches
+constexpr int64_t kRangesSearchAbove = 2048;
+
 }  // namespace
 
 // Keys per thread: small sorts use short chunks so that more blocks run.
 inline int sort_kpt(int64_t n_max) { return n_max <= (int64_t(1) << 20) ? 4 : 16; }
 
-size_t sort_scratch_bytes(int64_t n_max) {
+size_t sort_scratch_bytes(int64_t n_max, int64_t hist_cols) {
     const int64_t chunk = (int64_t)sort_kpt(n_max) * kNT;
-    const int64_t nb = (n_max + chunk - 1) / chunk;
+    const int64_t nb = std::max((n_max + chunk - 1) / chunk, hist_cols);
     return sizeof(uint32_t) * (size_t)(kRadix * (nb > 0 ? nb : 1) + kRadix);
 }
 
+// One digit pass.  hist_given: the digit histogram is already in hist with
+// hist_cols columns, hist_cols / nb of them per block of this pass (written by
+// the kernel that produced the keys), so the upsweep is skipped.
 template <int KPT>
 static void sort_pass(const uint32_t *src_k, const uint32_t *src_v, uint32_t *dst_k, uint32_t *dst_v,
                       const int64_t *n_dev, int64_t n_max, int shift, int bits, uint32_t *hist,
-                      uint32_t *digit_total, int64_t nb, hipStream_t s) {
-    hipLaunchKernelGGL((upsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, n_dev, n_max, shift,
-                       bits, hist);
-    hipLaunchKernelGGL(rowscan_kernel, dim3(kRadix), dim3(1024), 0, s, hist, nb, digit_total);
+                      uint32_t *digit_total, int64_t nb, int64_t hist_cols, hipStream_t s) {
+    if (hist_cols == 0) {
+        hipLaunchKernelGGL((upsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, n_dev, n_max, shift,
+                           bits, hist);
+        hist_cols = nb;
+    }
+    hipLaunchKernelGGL(rowscan_kernel, dim3(kRadix), dim3(1024), 0, s, hist, hist_cols, digit_total);
     hipLaunchKernelGGL((downsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, src_v, dst_k, dst_v,
-                       n_dev, n_max, shift, bits, (const uint32_t *)hist, (const uint32_t *)digit_total);
+                       n_dev, n_max, shift, bits, (const uint32_t *)hist, hist_cols, (int)(hist_cols / nb),
+                       (const uint32_t *)digit_total);
+}
+
+int radix_chunk(int64_t n_max) { return sort_kpt(n_max) * kNT; }
+
+int radix_first_bits(int begin_bit, int end_bit) {
+    const int total_bits = end_bit - begin_bit;
+    const int passes = (total_bits + 7) / 8;
+    return total_bits / passes;
 }
 
 hipError_t radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                           const int64_t *n_dev, int64_t n_max, int begin_bit, int end_bit,
-                          void *scratch, int *result_in_alt, hipStream_t s) {
+                          void *scratch, int *result_in_alt, hipStream_t s, int64_t first_hist_cols) {
     *result_in_alt = 0;
     const int kpt = sort_kpt(n_max);
     const int64_t chunk = (int64_t)kpt * kNT;
     const int64_t nb = (n_max + chunk - 1) / chunk;
     if (nb == 0 || end_bit <= begin_bit) return hipSuccess;
     uint32_t *hist = static_cast<uint32_t *>(scratch);
-    uint32_t *digit_total = hist + (size_t)kRadix * nb;
+    uint32_t *digit_total = hist + (size_t)kRadix * std::max(nb, first_hist_cols);
     uint32_t *src_k = keys, *src_v = vals, *dst_k = keys_alt, *dst_v = vals_alt;
     int alt = 0;
-    for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        const int bits = min(8, end_bit - shift);
+    // passes of near-equal width (13 tile bits: 7 + 6): narrower digits leave
+    // longer runs per digit in each block's output, so the scatter writes
+    // fuller cache lines
+    const int total_bits = end_bit - begin_bit;
+    const int passes = (total_bits + 7) / 8;
+    for (int p = 0, shift = begin_bit; p < passes; ++p) {
+        const int bits = (total_bits * (p + 1)) / passes - (total_bits * p) / passes;
+        const int64_t given = p == 0 ? first_hist_cols : 0;
         if (kpt == 4)
-            sort_pass<4>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, s);
+            sort_pass<4>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, given, s);
         else
-            sort_pass<16>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, s);
+            sort_pass<16>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, given, s);
         uint32_t *tk = src_k, *tv = src_v;
         src_k = dst_k; src_v = dst_v; dst_k = tk; dst_v = tv;
         alt ^= 1;
+        shift += bits;
     }
     *result_in_alt = alt;
     return hipGetLastError();
@@ -478,13 +537,19 @@ hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_
     return hipGetLastError();
 }
 
+int duplicate_window() { return kDupE; }
+
 hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
                             const Rec2D *rec, const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
                             const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,
-                            const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, hipStream_t s) {
+                            const int64_t *n_inst_dev, int64_t capacity, int32_t *overflow, uint32_t *hist,
+                            int hist_bits, int64_t hist_cols, hipStream_t s) {
     if (n_max == 0) return hipSuccess;
-    hipLaunchKernelGGL(duplicate_kernel, dim3(std::max(1u, blocks_for(capacity, kDupE))), dim3(kDupNT), 0, s, order, offsets,
-                       rect, rec, view_of, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow);
+    // with a histogram, one window per column (hist_cols * kDupE >= capacity)
+    const unsigned grid = hist ? (unsigned)hist_cols : std::max(1u, blocks_for(capacity, kDupE));
+    hipLaunchKernelGGL(duplicate_kernel, dim3(grid), dim3(kDupNT), 0, s, order, offsets,
+                       rect, rec, view_of, n_vis_dev, n_max, rp, tile_keys, ids, n_inst_dev, capacity, overflow, hist,
+                       hist_bits);
     return hipGetLastError();
 }
 
@@ -517,9 +582,13 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 
 hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
                               int32_t n_tiles, uint32_t *ranges, hipStream_t s) {
-    if (n_tiles > 0)
-        hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n_max + 1, 256)), dim3(256), 0, s, tile_keys, n_inst_dev,
-                           n_max, n_tiles, ranges);
+    if (n_tiles <= 0) return hipSuccess;
+    if (n_max > (int64_t)kRangesSearchAbove * n_tiles)
+        hipLaunchKernelGGL(ranges_search_kernel, dim3(blocks_for(n_tiles, 256)), dim3(256), 0, s, tile_keys,
+                           n_inst_dev, n_max, n_tiles, ranges);
+    else
+        hipLaunchKernelGGL(ranges_boundary_kernel, dim3(blocks_for(n_max + 1, 256)), dim3(256), 0, s, tile_keys,
+                           n_inst_dev, n_max, n_tiles, ranges);
     return hipGetLastError();
 }
 

@@ -221,6 +221,24 @@ def test_many_equal_depths_sorted_through_merges(ctx):
     ctx.release(st)
 
 
+def test_long_tile_lists_take_the_searched_ranges(ctx):
+    """A 32x32 image (4 tiles) under 20000 enlarged Gaussians: thousands of
+    instances per tile, so the ranges come from binary searches instead of key
+    boundaries; lists and ranges must still match the oracle bit for bit."""
+    sc = inputs.tiny_scene(20_000, seed=6)
+    sc.log_scale[:3] += 1.5
+    cam = inputs.look_at_camera(-5.0, 3.0, 32, 32)
+    _, _, st = ctx.render(to_dev(sc), cam, 0.5, _lib.default_cfg(tile_cull=0), keep_state=True)
+    b = ctx.binning(st)
+    torch.cuda.synchronize()
+    pre = oc.prepare(sc.arrays(), cam, 0.5, oracle_settings())
+    ids, _, ranges = obin.bin_gaussians(pre.rect, pre.depth, pre.visible, 32, 32, 16, 16)
+    assert ids.size > 2048 * 4
+    assert np.array_equal(b["sorted_ids"].cpu().numpy().astype(np.uint32), ids)
+    assert_same_ranges(b["tile_ranges"].cpu().numpy().astype(np.uint32), ranges)
+    ctx.release(st)
+
+
 def assert_same_ranges(got, ref):
     """Non-empty tiles must match exactly; an empty tile may be any [s, s)."""
     nonempty = ref[:, 1] > ref[:, 0]
