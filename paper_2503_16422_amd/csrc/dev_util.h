@@ -37,6 +37,15 @@ __device__ __forceinline__ float dpp_add_c(float v) {
     const int o = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, true);
     return v + __builtin_bit_cast(float, o);
 }
+// Sum over each row of 16 lanes, valid in every lane of the row: the first
+// four steps of the wavefront sum.
+__device__ __forceinline__ float row_sum16(float v) {
+    v = dpp_add_c<0xB1>(v);          // quad_perm(1,0,3,2)
+    v = dpp_add_c<0x4E>(v);          // quad_perm(2,3,0,1)
+    v = dpp_add_c<0x141>(v);         // row_half_mirror
+    v = dpp_add_c<0x140>(v);         // row_mirror
+    return v;
+}
 __device__ __forceinline__ float wave_sum_to_last(float v) {
     v = dpp_add_c<0xB1>(v);          // quad_perm(1,0,3,2)
     v = dpp_add_c<0x4E>(v);          // quad_perm(2,3,0,1)

@@ -31,9 +31,9 @@ struct BwdArgs {
 //   dL/da_i = T_i c_i.g - (S.g + T_final bg.g) / (1 - a_i)
 // then a_i = min(a_max, o_i G_i) -> (o_i, conic, centre).  A thread owns PPT
 // pixels of a column (as in the forward) and adds their terms before the
-// per-Gaussian sums are reduced across the wavefront (DPP, total in lane 63)
-// and added into the tile's LDS accumulators; one global add per value and
-// Gaussian leaves the tile after each batch.
+// per-Gaussian sums are reduced over each row of 16 lanes (DPP) and added into
+// the tile's LDS accumulators by one lane per row; one global add per value
+// and Gaussian leaves the tile after each batch.
 template <int TW, int TH, int BATCH, int PPT>
 __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) {
     constexpr int NT = TW * TH / PPT;
@@ -142,17 +142,18 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                 }
             }
             if (__ballot(hit) != 0ull) {
-                // wave sums (DPP, total in lane 63), then one LDS add per wave
-                du = wave_sum_to_last(du);
-                dv = wave_sum_to_last(dv);
-                da = wave_sum_to_last(da);
-                db = wave_sum_to_last(db);
-                dc = wave_sum_to_last(dc);
-                dop = wave_sum_to_last(dop);
-                dr = wave_sum_to_last(dr);
-                dg = wave_sum_to_last(dg);
-                dbl = wave_sum_to_last(dbl);
-                if (lane == 63) {
+                // sums over each row of 16 lanes (four DPP steps), then one
+                // LDS add per row: four lanes of one instruction per value
+                du = row_sum16(du);
+                dv = row_sum16(dv);
+                da = row_sum16(da);
+                db = row_sum16(db);
+                dc = row_sum16(dc);
+                dop = row_sum16(dop);
+                dr = row_sum16(dr);
+                dg = row_sum16(dg);
+                dbl = row_sum16(dbl);
+                if ((lane & 15) == 15) {
                     float *acc = s_acc + k * 9;
                     atomicAdd(acc + 0, du);
                     atomicAdd(acc + 1, dv);
