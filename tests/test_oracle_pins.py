@@ -712,3 +712,69 @@ def test_view_direction_points_from_camera_to_gaussian():
     dz = -1.0                      # camera at +z looks toward the origin
     expect = np.maximum(0.0, 0.5 + np.array([0.4, -0.3, 0.2]) * math.sqrt(3 / (4 * math.pi)) * dz)
     assert np.allclose(pre.rgb[0], expect, atol=1e-14)
+
+
+# P-VQ vector quantisation of the SH (post-processing) ------------------------
+def test_vq_layout_round_trip_and_distance_definition():
+    """Planes -> vectors is basis-major then channel, invertible; distances
+    equal the explicit sum over the 48 components."""
+    from oracle import vq
+    rng = np.random.default_rng(31)
+    sh = rng.standard_normal((16, 3, 7))
+    v = vq.sh_vectors(sh)
+    assert v.shape == (7, 48) and v[4, 3 * 5 + 2] == sh[5, 2, 4]
+    assert np.array_equal(vq.planes_from_vectors(v), sh)
+    c = rng.standard_normal((5, 48))
+    d = vq.squared_distances(v, c)
+    for i in range(7):
+        for j in range(5):
+            assert abs(d[i, j] - sum((v[i, k] - c[j, k]) ** 2 for k in range(48))) < 1e-12
+
+
+def test_vq_assign_brute_force_and_first_of_ties():
+    from oracle import vq
+    rng = np.random.default_rng(32)
+    x = rng.standard_normal((300, 48))
+    c = rng.standard_normal((17, 48))
+    c[9] = c[3]                                     # duplicate codebook entry: index 3 wins
+    a = vq.assign(x, c)
+    for i in range(300):
+        best = min(range(17), key=lambda j: (float(np.sum((x[i] - c[j]) ** 2)), j))
+        assert a[i] == best
+    assert not np.any(a == 9)
+
+
+def test_vq_kmeans_recovers_separated_clusters_and_is_a_fixed_point():
+    """Points scattered tightly around K well-separated centres, initialised
+    with one point of each cluster: Lloyd converges to the cluster means in one
+    step, assigns every point to its own cluster, and a further step changes
+    nothing; inertia never increases from a random start."""
+    from oracle import vq
+    rng = np.random.default_rng(33)
+    k, per = 6, 40
+    centres = rng.standard_normal((k, 48)) * 10.0
+    x = np.concatenate([centres[j] + 0.01 * rng.standard_normal((per, 48)) for j in range(k)])
+    truth = np.repeat(np.arange(k), per)
+    c, a = vq.kmeans(x, [j * per for j in range(k)], 3)
+    assert np.array_equal(a, truth)
+    for j in range(k):
+        assert np.allclose(c[j], x[truth == j].mean(axis=0), rtol=0, atol=1e-12)
+    assert np.array_equal(vq.update(x, vq.assign(x, c), c), c)
+    # inertia is non-increasing along Lloyd iterations
+    init = rng.choice(x.shape[0], k, replace=False)
+    prev = np.inf
+    cc = x[init].copy()
+    for _ in range(6):
+        aa = vq.assign(x, cc)
+        cur = vq.inertia(x, cc, aa)
+        assert cur <= prev + 1e-9
+        prev = cur
+        cc = vq.update(x, aa, cc)
+
+
+def test_vq_empty_cluster_keeps_its_vector():
+    from oracle import vq
+    x = np.array([[0.0] * 48, [1.0] * 48])
+    c = np.array([[0.1] * 48, [0.9] * 48, [50.0] * 48])
+    out = vq.update(x, vq.assign(x, c), c)
+    assert np.array_equal(out[2], c[2]) and np.allclose(out[0], 0.0) and np.allclose(out[1], 1.0)
