@@ -446,6 +446,22 @@ def main():
         log(f"[bench] grid: {grid}")
         extra["masked_scene_grid_fps"] = grid
 
+        # ---- SH vector quantisation (post-processing): codebook build, then the same frames --
+        k_vq, it_vq = 4096, 10
+        ctx.sh_kmeans(model, k_vq, 1)                                  # warm-up (allocations)
+        sync()
+        t0 = time.perf_counter()
+        code, assign = ctx.sh_kmeans(model, k_vq, it_vq)
+        sync()
+        vq_s = time.perf_counter() - t0
+        qmodel = model.quantized(assign, code)
+        q_fps, _ = timed_fps(ctx, qmodel, cams, frames, masks, frame_window, cfg, K, Wu, out)
+        extra["sh_vq"] = {"codebook": k_vq, "iterations": it_vq, "kmeans_s": round(vq_s, 4),
+                          "sh_bytes_dense": int(model.n * 192), "sh_bytes_vq": int(model.n * 4 + k_vq * 192),
+                          "masked_fps_vq": round(q_fps, 1)}
+        log(f"[bench] sh vq: {json.dumps(extra['sh_vq'])}")
+        del qmodel, code, assign
+
         # ---- dense unfiltered 3M scene -----------------------------------------------
         del model
         torch.cuda.empty_cache()

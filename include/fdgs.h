@@ -77,6 +77,15 @@ typedef struct {
     const float *sh;
     int64_t n;              /* 0 <= n < 2^31 */
     int32_t sh_degree;      /* 0..3; coefficients k >= (degree+1)^2 are not read */
+    /* Optional vector-quantised SH (the post-processing of Sec. 5, see
+     * fdgs_sh_kmeans): when sh_index is not NULL, Gaussian i's coefficients are
+     * sh_codebook[sh_index[i]][0..47] (basis-major, then channel; device,
+     * float32, 16-byte aligned), sh is not read and may be NULL, and an index
+     * >= sh_codebook_size reads the last entry.  fdgs_render_backward rejects
+     * such a model (FDGS_ERR_UNSUPPORTED).  Zero / NULL: plain SH planes. */
+    const uint32_t *sh_index;
+    const float *sh_codebook;
+    int64_t sh_codebook_size;
 } fdgs_model;
 
 /*
@@ -338,6 +347,23 @@ FDGS_API fdgs_status fdgs_variation_score(fdgs_ctx *ctx, const fdgs_model *model
  */
 FDGS_API fdgs_status fdgs_prune(fdgs_ctx *ctx, const float *score, int64_t n, int64_t n_keep, uint32_t *out_bits,
                                 uint32_t *out_idx, int64_t *out_count, hipStream_t stream);
+
+/*
+ * SH vector quantisation by Lloyd's k-means (the post-processing of Sec. 5:
+ * the paper quantises each Gaussian's SH with a codebook).  A Gaussian's SH
+ * vector is its 16 x 3 coefficients from model->sh (basis-major, then
+ * channel).  The codebook starts as the vectors of the k Gaussians init_index
+ * [k] names (device; indices >= n read the last Gaussian), then `iterations`
+ * times: assign every Gaussian to its nearest entry (squared L2 in float32,
+ * equal distances to the lower index), replace each entry by the mean of its
+ * members (float64 sum in index order; an entry without members is kept).
+ * Outputs: codebook [k][48] (device float32, 16-byte aligned) and assignment
+ * [n] (device; the nearest entry of the final codebook).  The whole
+ * computation is enqueued on `stream`; scratch is owned by ctx.
+ * Constraints: model->sh not NULL, 1 <= k <= 2^24, 0 <= iterations <= 1000.
+ */
+FDGS_API fdgs_status fdgs_sh_kmeans(fdgs_ctx *ctx, const fdgs_model *model, const uint32_t *init_index, int64_t k,
+                                    int32_t iterations, float *codebook, uint32_t *assignment, hipStream_t stream);
 
 /*
  * (8) Adam step for fine-tuning the kept Gaussians: for i < n (device float

@@ -26,7 +26,7 @@ EXPORTS = ["fdgs_last_error", "fdgs_version", "fdgs_create", "fdgs_destroy", "fd
            "fdgs_slice_4d", "fdgs_build_active_mask", "fdgs_render_forward", "fdgs_render_backward",
            "fdgs_state_release", "fdgs_state_binning", "fdgs_check_overflow", "fdgs_profile_enable",
            "fdgs_profile_read", "fdgs_render_batch", "fdgs_autotune", "fdgs_spatial_score",
-           "fdgs_variation_score", "fdgs_prune", "fdgs_adam_step"]
+           "fdgs_variation_score", "fdgs_prune", "fdgs_adam_step", "fdgs_sh_kmeans"]
 
 STAGES = ["preprocess", "compact", "depth_sort", "offsets", "duplicate", "tile_sort", "ranges", "composite",
           "bwd_composite", "bwd_preprocess"]
@@ -37,7 +37,8 @@ c_float_p = ctypes.POINTER(ctypes.c_float)
 class Model(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p), ("q_left", ctypes.c_void_p),
                 ("q_right", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p), ("sh", ctypes.c_void_p),
-                ("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32)]
+                ("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("sh_index", ctypes.c_void_p),
+                ("sh_codebook", ctypes.c_void_p), ("sh_codebook_size", ctypes.c_int64)]
 
 
 class Camera(ctypes.Structure):

@@ -134,6 +134,7 @@ struct fdgs_ctx {
     Buf mask_frames, mask_views, mask_scratch;
     Buf mask_flags, mask_img;      // contributed-mode visibility bytes and the keyframe image
     Buf prune_a, prune_b, prune_c, prune_d, prune_e, prune_times;   // score / prune work
+    Buf vq_scratch;                // k-means keys, values, cluster ranges, radix scratch
     int64_t *host_counts = nullptr;  // pinned
     // profiling
     int prof = 0;                  // 0 off, 1 stage events and counts, 2 also evaluated pairs
@@ -256,7 +257,8 @@ fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
     release(ctx->mask_scratch);
     release(ctx->mask_flags);
     release(ctx->mask_img);
-    for (Buf *b : {&ctx->prune_a, &ctx->prune_b, &ctx->prune_c, &ctx->prune_d, &ctx->prune_e, &ctx->prune_times})
+    for (Buf *b : {&ctx->prune_a, &ctx->prune_b, &ctx->prune_c, &ctx->prune_d, &ctx->prune_e, &ctx->prune_times,
+                   &ctx->vq_scratch})
         release(*b);
     release(ctx->prof_acc);
     for (auto &p : ctx->pending) {
@@ -279,8 +281,15 @@ fdgs_status check_model(const fdgs_model *m, const char *fn) {
         return fail(FDGS_ERR_INVALID_ARG, "%s: model n=%lld out of range", fn, (long long)m->n);
     if (m->sh_degree < 0 || m->sh_degree > 3)
         return fail(FDGS_ERR_INVALID_ARG, "%s: sh_degree %d not in 0..3", fn, m->sh_degree);
-    if (m->n > 0 && (!m->mean || !m->log_scale || !m->q_left || !m->q_right || !m->opacity_logit || !m->sh))
+    if (m->n > 0 && (!m->mean || !m->log_scale || !m->q_left || !m->q_right || !m->opacity_logit ||
+                     (!m->sh && !m->sh_index)))
         return fail(FDGS_ERR_INVALID_ARG, "%s: a model pointer is NULL", fn);
+    if (m->sh_index) {
+        if (!m->sh_codebook || m->sh_codebook_size < 1)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: sh_index needs sh_codebook and sh_codebook_size >= 1", fn);
+        if (reinterpret_cast<uintptr_t>(m->sh_codebook) % 16 != 0)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: sh_codebook must be 16-byte aligned", fn);
+    }
     return FDGS_OK;
 }
 
@@ -326,7 +335,9 @@ fdgs_status check_cfg(const fdgs_render_cfg *cfg, const char *fn) {
 }
 
 KModel kmodel(const fdgs_model *m) {
-    return KModel{m->mean, m->log_scale, m->q_left, m->q_right, m->opacity_logit, m->sh, m->n, m->sh_degree};
+    return KModel{m->mean,  m->log_scale, m->q_left,   m->q_right,     m->opacity_logit,
+                  m->sh,    m->n,         m->sh_degree, m->sh_index,   m->sh_codebook,
+                  m->sh_index ? m->sh_codebook_size : 0};
 }
 
 KCam kcam(const fdgs_camera *c) {
@@ -937,6 +948,8 @@ fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *
     if (!S) return fail(FDGS_ERR_STATE, "%s: state is not a live state of this context", fn);
     if (!S->has_forward) return fail(FDGS_ERR_STATE, "%s: state holds no forward pass", fn);
     if (!dL_drgb || !grads) return fail(FDGS_ERR_INVALID_ARG, "%s: dL_drgb or grads is NULL", fn);
+    if (S->model.sh_index)
+        return fail(FDGS_ERR_UNSUPPORTED, "%s: the forward used vector-quantised SH (no adjoint)", fn);
     if (S->model.n > 0 && (!grads->mean || !grads->log_scale || !grads->q_left || !grads->q_right ||
                            !grads->opacity_logit || !grads->sh))
         return fail(FDGS_ERR_INVALID_ARG, "%s: a gradient pointer is NULL", fn);
@@ -1146,6 +1159,27 @@ fdgs_status fdgs_prune(fdgs_ctx *ctx, const float *score, int64_t n, int64_t n_k
     HIP_TRY(launch_flags_to_bits(ctx->mask_flags.as<uint8_t>(), n, out_bits, stream));
     HIP_TRY(compact_bits(out_bits, n, out_idx, out_count, ctx->prune_e.p, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_sh_kmeans(fdgs_ctx *ctx, const fdgs_model *model, const uint32_t *init_index, int64_t k,
+                           int32_t iterations, float *codebook, uint32_t *assignment, hipStream_t stream) {
+    const char *fn = "fdgs_sh_kmeans";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (fdgs_status st = check_model(model, fn)) return st;
+    if (!model->sh) return fail(FDGS_ERR_INVALID_ARG, "%s: model->sh is NULL (nothing to quantise)", fn);
+    if (k < 1 || k > (int64_t(1) << 24)) return fail(FDGS_ERR_INVALID_ARG, "%s: k=%lld not in [1, 2^24]", fn, (long long)k);
+    if (iterations < 0 || iterations > 1000)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: iterations=%d not in [0, 1000]", fn, iterations);
+    if (!init_index || !codebook || !assignment)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: init_index, codebook or assignment is NULL", fn);
+    if (reinterpret_cast<uintptr_t>(codebook) % 16 != 0)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: codebook must be 16-byte aligned", fn);
+    if (model->n == 0) return FDGS_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(ensure(ctx->vq_scratch, vq_scratch_bytes(model->n, k)));
+    HIP_TRY(vq_kmeans(model->sh, model->n, init_index, k, iterations, codebook, assignment, ctx->vq_scratch.p,
+                      stream));
     return FDGS_OK;
 }
 

@@ -274,6 +274,29 @@ __device__ __forceinline__ void sh_eval(const float coef[48], int degree, float 
     }
 }
 
+// Coefficients of Gaussian g from the model: its SH planes or, for a
+// quantised model, its codebook entry (48 contiguous floats, 16-B aligned).
+__device__ __forceinline__ void load_sh_model(const KModel &m, int64_t g, float coef[48]) {
+    if (m.sh_index) {
+        const int64_t e = min((int64_t)m.sh_index[g], m.n_code - 1);
+        const float4 *src = reinterpret_cast<const float4 *>(m.sh_code + e * 48);
+        const int nk = (m.sh_degree + 1) * (m.sh_degree + 1);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const float4 v = src[q];
+            coef[4 * q] = v.x;
+            coef[4 * q + 1] = v.y;
+            coef[4 * q + 2] = v.z;
+            coef[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int i = 0; i < 48; ++i)
+            if (i / 3 >= nk) coef[i] = 0.0f;
+    } else {
+        load_sh(m.sh, m.n, g, m.sh_degree, coef);
+    }
+}
+
 __device__ __forceinline__ void sh_to_rgb(const float *sh, int64_t n, int64_t g, int degree,
                                           float dx, float dy, float dz, float rgb[3],
                                           float raw[3] = nullptr) {

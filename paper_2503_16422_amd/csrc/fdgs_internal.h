@@ -157,6 +157,11 @@ hipError_t launch_variation_score(const float *tv, const uint32_t *vol_key, cons
 hipError_t launch_prune_keys(const float *score, int64_t n, uint32_t *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_mark_first(const uint32_t *sorted_vals, int64_t n_keep, uint8_t *flags, hipStream_t s);
 
+// SH k-means (codebook [k][48], assignment [n]); scratch of vq_scratch_bytes(n, k).
+size_t vq_scratch_bytes(int64_t n, int64_t k);
+hipError_t vq_kmeans(const float *sh, int64_t n, const uint32_t *init, int64_t k, int32_t iterations, float *code,
+                     uint32_t *assign, void *scratch, hipStream_t s);
+
 // Adam (k_optim.hip).
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
                        float eps, int32_t step, hipStream_t s);

@@ -92,9 +92,9 @@ __device__ __forceinline__ bool preprocess_one(const ViewDesc &vd, int64_t j, co
         for (int k = 0; k < 3; ++k)
             d[k] = S.mean3[k] + (R[k] * vd.cam.t[0] + R[3 + k] * vd.cam.t[1] + R[6 + k] * vd.cam.t[2]);
         const double il = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        float rgb[3];
-        sh_to_rgb(vd.m.sh, vd.m.n, g, vd.m.sh_degree, (float)(d[0] * il), (float)(d[1] * il),
-                  (float)(d[2] * il), rgb);
+        float rgb[3], coef[48];
+        load_sh_model(vd.m, g, coef);
+        sh_eval(coef, vd.m.sh_degree, (float)(d[0] * il), (float)(d[1] * il), (float)(d[2] * il), rgb);
         const float uh = (float)Pr.u, vh = (float)Pr.v;
         Rec2D rec;
         rec.a = make_float4(uh, vh, (float)(Pr.u - (double)uh), (float)(Pr.v - (double)vh));

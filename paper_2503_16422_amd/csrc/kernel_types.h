@@ -20,6 +20,9 @@ struct KModel {
     const float *mean, *log_scale, *q_left, *q_right, *logit, *sh;
     int64_t n;
     int32_t sh_degree;
+    const uint32_t *sh_index;   // optional: SH from sh_code[sh_index[g]] (48 floats per entry)
+    const float *sh_code;
+    int64_t n_code;
 };
 
 // Per visible Gaussian record consumed by the compositor (48 B, 16-B aligned).

@@ -47,7 +47,8 @@ class GaussianModel:
 
     FIELDS = ("mean", "log_scale", "q_left", "q_right", "opacity_logit", "sh")
 
-    def __init__(self, mean, log_scale, q_left, q_right, opacity_logit, sh, sh_degree: int = 3):
+    def __init__(self, mean, log_scale, q_left, q_right, opacity_logit, sh, sh_degree: int = 3,
+                 sh_index=None, sh_codebook=None):
         self.mean, self.log_scale = mean, log_scale
         self.q_left, self.q_right = q_left, q_right
         self.opacity_logit, self.sh = opacity_logit, sh
@@ -59,6 +60,21 @@ class GaussianModel:
             t = getattr(self, k)
             if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError(f"{k}: need a contiguous float32 device tensor of shape {shp}")
+        # optional vector-quantised SH: int32 index per Gaussian into a [K, 48] float32 codebook
+        self.sh_index, self.sh_codebook = sh_index, sh_codebook
+        if (sh_index is None) != (sh_codebook is None):
+            raise ValueError("sh_index and sh_codebook go together")
+        if sh_index is not None:
+            if tuple(sh_index.shape) != (n,) or sh_index.dtype != torch.int32 or not sh_index.is_cuda:
+                raise ValueError("sh_index: need an int32 device tensor of shape (n,)")
+            if (sh_codebook.dim() != 2 or sh_codebook.shape[1] != 48 or sh_codebook.dtype != torch.float32
+                    or not sh_codebook.is_contiguous() or not sh_codebook.is_cuda):
+                raise ValueError("sh_codebook: need a contiguous float32 device tensor of shape (K, 48)")
+
+    def quantized(self, sh_index, sh_codebook) -> "GaussianModel":
+        """The same Gaussians with SH read from a codebook."""
+        return GaussianModel(self.mean, self.log_scale, self.q_left, self.q_right, self.opacity_logit, self.sh,
+                             self.sh_degree, sh_index, sh_codebook)
 
     @property
     def n(self) -> int:
@@ -76,6 +92,10 @@ class GaussianModel:
             setattr(m, k, getattr(self, k).data_ptr())
         m.n = self.n
         m.sh_degree = self.sh_degree
+        if self.sh_index is not None:
+            m.sh_index = self.sh_index.data_ptr()
+            m.sh_codebook = self.sh_codebook.data_ptr()
+            m.sh_codebook_size = int(self.sh_codebook.shape[0])
         return m
 
     def tensors(self):
@@ -290,6 +310,23 @@ class Context:
                                        ctypes.c_int64(int(n_keep)), _ptr(bits), _ptr(idx), _ptr(count),
                                        _stream(self.device)))
         return bits, idx, count
+
+    def sh_kmeans(self, model: GaussianModel, k: int, iterations: int, init_index: Optional[torch.Tensor] = None,
+                  seed: int = 0):
+        """Vector quantisation of the SH vectors: (codebook [k, 48], assignment [n] int32).  The
+        initial codebook is the vectors of init_index (default: k distinct Gaussians drawn with
+        `seed`)."""
+        n = model.n
+        if init_index is None:
+            rng = np.random.default_rng(seed)
+            init_index = torch.from_numpy(rng.choice(n, size=k, replace=k > n).astype(np.int32)).to(self.device)
+        code = torch.empty((k, 48), dtype=torch.float32, device=self.device)
+        assign = torch.empty((max(n, 1),), dtype=torch.int32, device=self.device)
+        ms = model.struct()
+        _lib.check(self.lib.fdgs_sh_kmeans(self.handle, ctypes.byref(ms), _ptr(init_index.contiguous()),
+                                           ctypes.c_int64(k), int(iterations), _ptr(code), _ptr(assign),
+                                           _stream(self.device)))
+        return code, assign[:n]
 
     def check_overflow(self):
         _lib.check(self.lib.fdgs_check_overflow(self.handle, _stream(self.device)))

@@ -59,13 +59,14 @@ def test_null_context_rejected_without_gpu(lib):
                           None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_adam_step(None, None, None, None, None, ctypes.c_int64(0), ctypes.c_float(0.1), ctypes.c_float(0.9),
                               ctypes.c_float(0.999), ctypes.c_float(1e-8), 1, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_sh_kmeans(None, None, None, ctypes.c_int64(1), 1, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_create(None, 0) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_destroy(None) == _lib.FDGS_OK
 
 
 def test_struct_layouts_match_header():
     # sizes follow the C layout rules for the declared members
-    assert ctypes.sizeof(_lib.Model) == 6 * 8 + 8 + 8
+    assert ctypes.sizeof(_lib.Model) == 6 * 8 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(_lib.Camera) == 9 * 8 + 3 * 8 + 5 * 8 + 2 * 4
     assert ctypes.sizeof(_lib.RenderCfg) == 4 * 4 + 3 * 4 + 4 * 4 + 4 + 4 + 4 + 8
     assert ctypes.sizeof(_lib.Grads) == 6 * 8
