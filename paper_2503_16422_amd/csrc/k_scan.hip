@@ -208,14 +208,17 @@ __global__ void __launch_bounds__(kNT) compact_visible_kernel(const uint8_t *vis
 
 // --- compaction of active-set bits -----------------------------------------
 // Each block covers kChunk Gaussians (kChunk/32 bit words).
-__global__ void __launch_bounds__(kNT) bits_count_kernel(const uint32_t *bits, int64_t nw,
+// Bits at positions >= n (the tail of the last word) are not counted, as the
+// compaction does not emit them.
+__global__ void __launch_bounds__(kNT) bits_count_kernel(const uint32_t *bits, int64_t n, int64_t nw,
                                                          uint64_t *partial) {
     __shared__ uint64_t tmp[kNT / 64 + 1];
     constexpr int kWords = kChunk / 32;
     const int64_t w0 = (int64_t)blockIdx.x * kWords;
+    const uint32_t tail = (n & 31) ? ((1u << (n & 31)) - 1u) : 0xffffffffu;
     uint64_t c = 0;
     for (int k = threadIdx.x; k < kWords; k += kNT)
-        if (w0 + k < nw) c += __popc(bits[w0 + k]);
+        if (w0 + k < nw) c += __popc(bits[w0 + k] & (w0 + k == nw - 1 ? tail : 0xffffffffu));
     uint64_t total;
     block_exclusive_sum<kNT>(c, tmp, &total);
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
@@ -290,7 +293,7 @@ hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t 
     uint64_t *partial = static_cast<uint64_t *>(scratch);
     const int64_t nw = (n + 31) / 32;
     if (nb > 0)
-        hipLaunchKernelGGL(bits_count_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, nw, partial);
+        hipLaunchKernelGGL(bits_count_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, n, nw, partial);
     hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, count, (uint32_t *)nullptr,
                        (int64_t)0, (uint32_t *)nullptr);
     if (nb > 0)

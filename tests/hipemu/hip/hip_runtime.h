@@ -104,6 +104,26 @@ inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); retu
 inline double __longlong_as_double(long long x) { double d; std::memcpy(&d, &x, 8); return d; }
 inline long long __double_as_longlong(double d) { long long x; std::memcpy(&x, &d, 8); return x; }
 
+inline uint32_t emu_mbcnt_lo(uint32_t m, uint32_t base) {
+    const int l = threadIdx.x & 63;
+    const uint32_t below = l >= 32 ? 0xffffffffu : ((1u << l) - 1u);
+    return base + (uint32_t)__builtin_popcount(m & below);
+}
+inline uint32_t emu_mbcnt_hi(uint32_t m, uint32_t base) {
+    const int l = threadIdx.x & 63;
+    const uint32_t below = l < 32 ? 0u : ((uint32_t)((1ull << (l - 32)) - 1ull));
+    return base + (uint32_t)__builtin_popcount(m & below);
+}
+#define __builtin_amdgcn_mbcnt_lo(m, b) emu_mbcnt_lo((m), (b))
+#define __builtin_amdgcn_mbcnt_hi(m, b) emu_mbcnt_hi((m), (b))
+#define __HIP_MEMORY_SCOPE_AGENT 0
+#define __HIP_MEMORY_SCOPE_WORKGROUP 0
+template <typename T> inline T __hip_atomic_load(const T *p, int, int) {
+    return std::atomic_ref<T>(*const_cast<T *>(p)).load();
+}
+template <typename T, typename U> inline void __hip_atomic_store(T *p, U v, int, int) {
+    std::atomic_ref<T>(*p).store((T)v);
+}
 template <typename T> inline T atomicAdd(T *p, T v) { return std::atomic_ref<T>(*p).fetch_add(v); }
 template <typename T> inline T atomicOr(T *p, T v) { return std::atomic_ref<T>(*p).fetch_or(v); }
 template <typename T> inline T atomicMin(T *p, T v) {

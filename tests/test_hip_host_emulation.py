@@ -1,7 +1,8 @@
-"""The depth-bucket kernels run on the host through an emulation of the HIP
-device API (tests/hipemu), compiled with g++ and AddressSanitizer: every
-access of the kernel source is bounds-checked and the result is compared with
-a plain sort by (depth, position).  No GPU is involved."""
+"""Kernels run on the host through an emulation of the HIP device API
+(tests/hipemu), compiled with g++ and AddressSanitizer: every access of the
+kernel source is bounds-checked and the results are compared with plain
+host computations (a sort by (depth, position); exclusive scans and
+compaction).  No GPU is involved."""
 import os
 import re
 import shutil
@@ -21,13 +22,23 @@ def host_source(name: str) -> str:
     return re.sub(r"extern __shared__ (\w+) (\w+)\[\];", r"\1 *\2 = (\1 *)g_dyn_lds;", src)
 
 
-@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
-def test_bucket_depth_order_kernels_on_host(tmp_path):
-    (tmp_path / "k_bucket_host.inc").write_text(host_source("k_bucket.hip"))
-    exe = str(tmp_path / "bucket_check")
+def run_on_host(tmp_path, kernel_file: str, check: str):
+    inc = os.path.splitext(kernel_file)[0] + "_host.inc"
+    (tmp_path / inc).write_text(host_source(kernel_file))
+    exe = str(tmp_path / os.path.splitext(check)[0])
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address", "-I", str(tmp_path), "-I", EMU, "-I", CSRC,
-           "-I", os.path.join(ROOT, "include"), os.path.join(EMU, "bucket_check.cpp"), "-o", exe, "-pthread"]
+           "-I", os.path.join(ROOT, "include"), os.path.join(EMU, check), "-o", exe, "-pthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_bucket_depth_order_kernels_on_host(tmp_path):
+    run_on_host(tmp_path, "k_bucket.hip", "bucket_check.cpp")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_scans_on_host(tmp_path):
+    run_on_host(tmp_path, "k_scan.hip", "scan_check.cpp")
