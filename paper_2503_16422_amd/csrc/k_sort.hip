@@ -218,9 +218,10 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
     const int64_t n = count_of(n_dev, n_max);
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j + 1 >= n) return;
-    const uint32_t k = keys32[j];
-    if (keys32[j + 1] != k) return;
-    if (j > 0 && keys32[j - 1] == k) return;      // not the start of the run
+    // the three keys are loaded together
+    const uint32_t k = keys32[j], kn = keys32[j + 1], kp = keys32[j > 0 ? j - 1 : j];
+    if (kn != k) return;
+    if (j > 0 && kp == k) return;                 // not the start of the run
     int64_t e = j + 1;
     while (e < n && e - j <= kMaxTieRun && keys32[e] == k) ++e;
     if (e - j > kMaxTieRun) {

@@ -1,7 +1,7 @@
 // Host emulation of the HIP device API, for checking kernels on the CPU (test
-// infrastructure only).  Each block runs on its own set of std::threads, one per
-// work-item, and blocks run one after another, so __shared__ variables can be
-// function statics; __syncthreads is a std::barrier over the block; wavefront
+// infrastructure only).  A block runs on std::threads, one per work-item, and
+// blocks run one after another, so __shared__ variables can be function
+// statics; __syncthreads is a std::barrier over the block; wavefront
 // shuffles and ballots go through a per-wavefront exchange buffer with a
 // barrier over its 64 work-items; atomics are std::atomic_ref.  A work-item
 // that returns drops out of every barrier, as an exited wavefront does.
@@ -139,29 +139,45 @@ template <typename T> inline T atomicMax(T *p, T v) {
 using std::max;
 using std::min;
 
+// One std::thread per work-item of a block, reused for every block of the
+// launch: after a block, all work-items meet at an end barrier, work-item 0
+// sets up fresh block and wavefront barriers and a fresh dynamic shared buffer,
+// and the next block starts.
 template <typename... KArgs, typename... Args>
 void cpu_launch(void (*k)(KArgs...), dim3 grid, dim3 block, size_t shmem, Args... args) {
-    blockDim.x = block.x; gridDim.x = grid.x;
-    for (unsigned b = 0; b < grid.x; ++b) {
-        std::vector<char> lds(shmem ? shmem : 1);
-        g_dyn_lds = shmem ? lds.data() : nullptr;
-        std::barrier<> bar(block.x);
-        g_block_barrier = &bar;
+    blockDim.x = block.x;
+    gridDim.x = grid.x;
+    if (grid.x == 0) return;
+    std::unique_ptr<std::barrier<>> blk;
+    std::vector<char> lds;
+    auto setup = [&]() {
+        blk = std::make_unique<std::barrier<>>(block.x);
+        g_block_barrier = blk.get();
         g_waves.clear();
         for (unsigned w = 0; w < (block.x + 63) / 64; ++w) {
             auto x = std::make_unique<WaveX>();
             x->bar = std::make_unique<std::barrier<>>(std::min(64u, block.x - 64 * w));
             g_waves.push_back(std::move(x));
         }
-        std::vector<std::thread> ts;
-        for (unsigned t = 0; t < block.x; ++t)
-            ts.emplace_back([&, t, b]() {
-                threadIdx.x = t; blockIdx.x = b;
+        lds.assign(shmem ? shmem : 1, 0);
+        g_dyn_lds = shmem ? lds.data() : nullptr;
+    };
+    setup();
+    std::barrier<> end_bar(block.x);
+    std::vector<std::thread> ts;
+    for (unsigned t = 0; t < block.x; ++t)
+        ts.emplace_back([&, t]() {
+            threadIdx.x = t;
+            for (unsigned b = 0; b < grid.x; ++b) {
+                blockIdx.x = b;
                 k(args...);
                 g_waves[t / 64]->bar->arrive_and_drop();
                 g_block_barrier->arrive_and_drop();
-            });
-        for (auto &th : ts) th.join();
-    }
+                end_bar.arrive_and_wait();
+                if (t == 0 && b + 1 < grid.x) setup();
+                end_bar.arrive_and_wait();
+            }
+        });
+    for (auto &th : ts) th.join();
 }
 #define hipLaunchKernelGGL(k, grid, block, shmem, stream, ...) cpu_launch(k, dim3(grid), dim3(block), (size_t)(shmem), __VA_ARGS__)

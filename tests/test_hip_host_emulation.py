@@ -22,7 +22,7 @@ def host_source(name: str) -> str:
     return re.sub(r"extern __shared__ (\w+) (\w+)\[\];", r"\1 *\2 = (\1 *)g_dyn_lds;", src)
 
 
-def run_on_host(tmp_path, kernel_file: str, check: str):
+def run_on_host(tmp_path, kernel_file: str, check: str, *args: str):
     inc = os.path.splitext(kernel_file)[0] + "_host.inc"
     (tmp_path / inc).write_text(host_source(kernel_file))
     exe = str(tmp_path / os.path.splitext(check)[0])
@@ -30,7 +30,7 @@ def run_on_host(tmp_path, kernel_file: str, check: str):
            "-I", os.path.join(ROOT, "include"), os.path.join(EMU, check), "-o", exe, "-pthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=1200)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
 
 
@@ -42,3 +42,11 @@ def test_bucket_depth_order_kernels_on_host(tmp_path):
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 def test_scans_on_host(tmp_path):
     run_on_host(tmp_path, "k_scan.hip", "scan_check.cpp")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_tile_binning_kernels_on_host(tmp_path):
+    """Emission, stable tile sort and ranges at an exact capacity; with
+    FDGS_HOST_EMU_FULL=1 also above 2^20 instances, where the emission writes
+    the sort's first-digit histogram (several minutes in the emulation)."""
+    run_on_host(tmp_path, "k_sort.hip", "sort_check.cpp", *(["full"] if os.environ.get("FDGS_HOST_EMU_FULL") else []))
