@@ -107,7 +107,8 @@ typedef struct {
  * brackets.  Screen tiles and the LDS batch only change speed, never the image.
  */
 typedef struct {
-    int32_t tile_w, tile_h;     /* one of 8x8, 16x16, 32x8            [16x16] */
+    int32_t tile_w, tile_h;     /* one of 8x8, 16x16, 32x8, 32x16,
+                                   32x32                         [16x16] */
     int32_t batch;              /* Gaussians staged in LDS: 64/128/256   [128] */
     int32_t pixels_per_thread;  /* 1, 2 or 4 pixels of a column per thread in
                                    the forward compositor; 8x8 tiles always
@@ -289,9 +290,10 @@ FDGS_API fdgs_status fdgs_render_batch(fdgs_ctx *ctx, const fdgs_model *scenes, 
                                        int32_t use_graph, float *out_rgb, hipStream_t stream);
 
 /*
- * Autotuner: renders the batch with every tile shape (8x8, 16x16, 32x8), LDS
- * batch (64, 128, 256), pixels-per-thread choice (1, 2, 4; 1 only for 8x8)
- * and compositor schedule (1, 0): 42 configurations, each timed with HIP
+ * Autotuner: renders the batch with every tile shape (8x8, 16x16, 32x8,
+ * 32x16, 32x32), LDS batch (64, 128, 256), pixels-per-thread choice (1, 2, 4;
+ * 1 only for 8x8) and compositor schedule (1, 0): 78 configurations, each
+ * timed with HIP
  * events (best of `repeats`).  It checks that every
  * configuration's images are bit-identical to the first one's, and writes the
  * fastest into *inout_cfg (other fields are kept).  results (host, may be

@@ -74,7 +74,9 @@ void release(Buf &b) {
 constexpr int32_t kDefaultPpt = 2;
 constexpr int64_t kBucketMaxN = int64_t(1) << 20;   // largest processed count ordered by buckets
 
-bool valid_tile(int w, int h) { return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8); }
+bool valid_tile(int w, int h) {
+    return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && (h == 8 || h == 16 || h == 32));
+}
 
 int bits_for(int64_t v) {   // bits needed to represent values in [0, v)
     int b = 0;
@@ -313,7 +315,7 @@ fdgs_status check_camera(const fdgs_camera *c, const char *fn) {
 fdgs_status check_cfg(const fdgs_render_cfg *cfg, const char *fn) {
     if (!cfg) return fail(FDGS_ERR_INVALID_ARG, "%s: cfg is NULL", fn);
     if (!valid_tile(cfg->tile_w, cfg->tile_h))
-        return fail(FDGS_ERR_INVALID_ARG, "%s: tile %dx%d not one of 8x8, 16x16, 32x8", fn, cfg->tile_w,
+        return fail(FDGS_ERR_INVALID_ARG, "%s: tile %dx%d not one of 8x8, 16x16, 32x8, 32x16, 32x32", fn, cfg->tile_w,
                     cfg->tile_h);
     if (cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
         return fail(FDGS_ERR_INVALID_ARG, "%s: batch %d not one of 64, 128, 256", fn, cfg->batch);
@@ -875,7 +877,7 @@ fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_sce
     HIP_TRY(ensure(ctx->tune_diff, sizeof(unsigned long long)));
     struct Cand { int tw, th, b, ppt, sched; };
     std::vector<Cand> cands;
-    const int shapes[3][2] = {{16, 16}, {8, 8}, {32, 8}};
+    const int shapes[5][2] = {{16, 16}, {8, 8}, {32, 8}, {32, 16}, {32, 32}};
     for (int sched : {1, 0})
         for (auto &sh : shapes)
             for (int b : {64, 128, 256})

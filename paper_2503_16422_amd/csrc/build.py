@@ -31,7 +31,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-un
 # Per-file flags.  The adjoint compositor adds each wavefront's reduced value
 # into LDS from one lane; LLVM's atomic optimizer would wrap every such add in
 # a lane loop (readlane / mbcnt / exec juggling), so it is off for that file.
-EXTRA = {"k_composite_bwd.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+# The forward compositor asks for eight wavefronts per SIMD where its LDS use
+# allows fewer; the compiler's note that it cannot meet that is expected.
+EXTRA = {"k_composite_bwd.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+         "k_composite.hip": ["-Wno-pass-failed"]}
 
 
 def _compile(src: str) -> str:

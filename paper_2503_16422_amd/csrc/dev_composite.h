@@ -61,6 +61,16 @@ __device__ __forceinline__ float after(float T, float alpha) { return fmaf(-alph
             else if (batch == 128) LAUNCH<32, 8, 128>(ARGS, n_tiles, s);                        \
             else if (batch == 256) LAUNCH<32, 8, 256>(ARGS, n_tiles, s);                        \
             else ok = false;                                                                    \
+        } else if (key == 32016) {                                                              \
+            if (batch == 64) LAUNCH<32, 16, 64>(ARGS, n_tiles, s);                              \
+            else if (batch == 128) LAUNCH<32, 16, 128>(ARGS, n_tiles, s);                       \
+            else if (batch == 256) LAUNCH<32, 16, 256>(ARGS, n_tiles, s);                       \
+            else ok = false;                                                                    \
+        } else if (key == 32032) {                                                              \
+            if (batch == 64) LAUNCH<32, 32, 64>(ARGS, n_tiles, s);                              \
+            else if (batch == 128) LAUNCH<32, 32, 128>(ARGS, n_tiles, s);                       \
+            else if (batch == 256) LAUNCH<32, 32, 256>(ARGS, n_tiles, s);                       \
+            else ok = false;                                                                    \
         } else {                                                                                \
             ok = false;                                                                         \
         }                                                                                       \

@@ -111,6 +111,26 @@ __device__ inline bool ellipse_row_span(const CullEllipse &e, int r0, int r1, in
     return true;
 }
 
+// Pixel columns [*p0, *p1] (within [x0, x1]) that the ellipse may reach over
+// rows [r0, r1]; false when it reaches no pixel centre of the block.  Every
+// point at height dy has a quadratic form of at least (det / a) dy^2, so a
+// band whose nearest height to the centre already exceeds the level holds no
+// such pixel; otherwise the band's column span decides.
+__device__ inline bool ellipse_band_columns(const CullEllipse &e, int r0, int r1, int x0, int x1, int *p0,
+                                            int *p1) {
+#pragma clang fp contract(off)
+    if (!(e.a > 0.0f)) {
+        *p0 = x0;
+        *p1 = x1;
+        return true;
+    }
+    const float d0 = (float)(((double)r0 + 0.5) - e.v), d1 = (float)(((double)r1 + 0.5) - e.v);
+    const float dn = (d0 <= 0.0f && d1 >= 0.0f) ? 0.0f : fminf(fabsf(d0), fabsf(d1));
+    const float aq = e.a * e.q, tn = e.det * (dn * dn);
+    if ((aq - tn) + 1e-6f * (aq + tn) < 0.0f) return false;
+    return ellipse_row_span(e, r0, r1, x0, x1, p0, p1);
+}
+
 // Tile columns [*c0, *c1] of tile row ty for a record with pixel rectangle
 // rect (x0, y0, x1, y1); false when the row is empty.
 __device__ inline bool tile_row_span(const CullEllipse &e, int4 rect, int ty, int tw, int th, int *c0, int *c1) {

@@ -17,6 +17,7 @@
 #include <algorithm>
 
 #include "dev_composite.h"
+#include "dev_cull.h"
 #include "dev_util.h"
 #include "fdgs_internal.h"
 
@@ -44,9 +45,46 @@ struct CompArgs {
     float *weight;               // kWeight: per processed entry, += sum of alpha T
 };
 
-// Thread layout: PPT consecutive pixels of one column per thread
+// Thread layout: each wavefront owns a CW x CH block ("cell") of the tile and
+// each of its threads PPT consecutive pixels of one column of the cell
 // (TW x TH / PPT threads); the column's dx terms and the LDS reads of a record
-// are shared by the thread's PPT pixels.
+// are shared by the thread's PPT pixels.  Cells are 16 pixels wide where the
+// tile allows, so several wavefronts split a tile into blocks that a record's
+// footprint often misses: with several pixels per thread, the staging marks
+// in one bitmap per wavefront the records whose ellipse reaches its cell, and
+// the wavefront walks only those (a scalar bit scan per record).
+template <int TW, int TH, int PPT>
+struct Cells {
+    static constexpr int CW = (TW >= 16 && TH >= 4 * PPT) ? 16 : TW;
+    static constexpr int CH = 64 * PPT / CW;
+    static constexpr int CX = TW / CW;
+    static constexpr int NW = CX * (TH / CH);
+    static_assert(TW % CW == 0 && TH % CH == 0 && NW * 64 * PPT == TW * TH, "whole cells per tile");
+};
+
+// Bit w set when the record's footprint ellipse reaches a pixel of wavefront
+// w's cell of the tile with origin (x0, y0) (every bit when tile culling is
+// off, or the ellipse is not usable for it).  One column span per band of
+// cell rows, then a range test per cell of the band.
+template <int TW, int TH, int PPT>
+__device__ __forceinline__ uint32_t reached_cells(const Rec2D &r, const RenderParams &rp, int x0, int y0) {
+    using C = Cells<TW, TH, PPT>;
+    const CullEllipse e = cull_ellipse(r, rp);
+    uint32_t m = 0;
+#pragma unroll 1
+    for (int band = 0; band < C::NW / C::CX; ++band) {
+        const int r0 = y0 + band * C::CH;
+        int p0 = x0, p1 = x0 + TW - 1;
+        if (!ellipse_band_columns(e, r0, r0 + C::CH - 1, x0, x0 + TW - 1, &p0, &p1)) continue;
+#pragma unroll
+        for (int cx = 0; cx < C::CX; ++cx) {
+            const int c0 = x0 + cx * C::CW;
+            if (p0 <= c0 + C::CW - 1 && p1 >= c0) m |= 1u << (band * C::CX + cx);
+        }
+    }
+    return m;
+}
+
 // What a compositor instance records beyond colour and transmittance.
 enum CompMode {
     kPlain = 0,   // nothing
@@ -62,11 +100,18 @@ template <int TW, int TH, int BATCH, int PPT, int MODE>
 __device__ __forceinline__ void composite_item(const CompArgs &a, int item, float4 *s_rec) {
     constexpr int NT = TW * TH / PPT;
     static_assert(NT % 64 == 0, "whole wavefronts per tile");
+    using C = Cells<TW, TH, PPT>;
+    // per-wavefront bitmaps of the batch's records that reach its cell (several
+    // pixels per thread; a single-pixel thread branches per pixel instead)
+    constexpr bool kBits = C::NW > 1 && PPT > 1;
+    constexpr int kWords = BATCH / 64;
+    __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
     const int n_tiles = a.rp.tiles_x * a.rp.tiles_y;
     const int view = item / n_tiles;
     const int tile = item - view * n_tiles;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
-    const int lx = threadIdx.x % TW, ly0 = (threadIdx.x / TW) * PPT;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = (int)threadIdx.x % 64;
+    const int lx = (wave % C::CX) * C::CW + lane % C::CW, ly0 = (wave / C::CX) * C::CH + (lane / C::CW) * PPT;
     const int px = tx * TW + lx, py0 = ty * TH + ly0;
     // Offsets are taken from the origin of the enclosing 32x32 block, which is
     // the same for every tile shape, so a pixel's arithmetic does not depend on
@@ -93,7 +138,9 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
         T[p] = 1.0f;
         C0[p] = C1[p] = C2[p] = 0.0f;
         last[p] = 0;
-        stop[p] = end - start;
+        // evaluated pairs (profiling): a single-pixel thread evaluates its list up
+        // to its stop; a multi-pixel thread counts the records it evaluates live
+        stop[p] = PPT == 1 ? end - start : 0u;
         const bool inside = px < a.W && py0 + p < a.H;
         thr[p] = inside ? tmin : kInf;
         all_done = all_done && !inside;
@@ -107,16 +154,33 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
         }
         if (__syncthreads_count(!all_done) == 0) break;
         const int cnt = (int)min((uint32_t)BATCH, end - base);
-        for (int k = threadIdx.x; k < cnt; k += NT) {
-            const Rec2D r = a.rec[a.ids[base + k]];
-            const float4 q = staged_conic(r);
-            s_rec[3 * k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
-            s_rec[3 * k + 1] = make_float4(q.z, q.w, r.c.x, r.c.y);
-            s_rec[3 * k + 2] = make_float4(r.c.z, __uint_as_float(a.ids[base + k]), 0.0f, 0.0f);
+        // staging: thread t stages records t, t + NT, ... of the batch; with several
+        // cells per tile, each wavefront also records, per target wavefront, which
+        // of its 64 records reach that wavefront's cell (one ballot per cell)
+        for (int k0 = 0; k0 < cnt; k0 += NT) {
+            const int k = k0 + (int)threadIdx.x;
+            uint32_t cells = 0u;
+            if (k < cnt) {
+                const uint32_t id = a.ids[base + k];
+                const Rec2D r = a.rec[id];
+                const float4 q = staged_conic(r);
+                if constexpr (kBits) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
+                s_rec[3 * k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
+                s_rec[3 * k + 1] = make_float4(q.z, q.w, r.c.x, r.c.y);
+                s_rec[3 * k + 2] = make_float4(r.c.z, __uint_as_float(id), 0.0f, 0.0f);
+            }
+            if constexpr (kBits) {
+                const int word = k0 / 64 + wave;
+#pragma unroll
+                for (int w = 0; w < C::NW; ++w) {
+                    const uint64_t m = __ballot((cells >> w) & 1u);
+                    if (lane == 0 && word < kWords) s_bits[w * kWords + word] = m;
+                }
+            }
         }
         __syncthreads();
-        if (!all_done) {
-            if constexpr (PPT == 1) {
+        if constexpr (PPT == 1) {
+            if (!all_done) {
                 for (int k = 0; k < cnt; ++k) {
                     const float4 g = s_rec[3 * k];
                     const float4 h = s_rec[3 * k + 1];
@@ -147,59 +211,84 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     }
                     if constexpr (WEIGHT) atomicAdd(&a.weight[__float_as_uint(s_rec[3 * k + 2].y)], w);
                 }
+            }
+        } else if (__ballot(!all_done) != 0ull) {
+            // several pixels: select-based updates, no branches or lane masks per
+            // pixel, and control flow uniform over the wavefront (lanes whose pixels
+            // stopped run along with w = 0), so the wavefront sums see every lane
+            auto blend = [&](int k) {
+                const float4 g = s_rec[3 * k];
+                const float4 h = s_rec[3 * k + 1];
+                const float4 q = make_float4(g.z, g.w, h.x, h.y);
+                const float cb = s_rec[3 * k + 2].x;
+                const float dx = fx - g.x;
+                const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
+                const uint32_t pos = base + k - start + 1;
+                bool blended = false;
+                float wsum = 0.0f;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    // alpha below alpha_min enters as 0: the test then keeps T (>= t_min), w = 0
+                    const float e = exp2_at(q, A, B, fy[p] - g.y);
+                    const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
+                    const float al = alpha >= amin ? alpha : 0.0f;
+                    const float test = after(T[p], al);
+                    const bool ok = test >= thr[p];
+                    const float w = ok ? al * T[p] : 0.0f;
+                    C0[p] = fmaf(h.z, w, C0[p]);
+                    C1[p] = fmaf(h.w, w, C1[p]);
+                    C2[p] = fmaf(cb, w, C2[p]);
+                    if constexpr (LAST) last[p] = w > 0.0f ? pos : last[p];   // w >= alpha_min t_min > 0
+                    if constexpr (COUNT) stop[p] += thr[p] < kInf ? 1u : 0u;
+                    T[p] = ok ? test : T[p];
+                    thr[p] = ok ? thr[p] : kInf;
+                    if constexpr (MARK) blended = blended || w > 0.0f;
+                    if constexpr (WEIGHT) wsum += w;
+                }
+                if constexpr (WEIGHT) {
+                    // one wave sum, one atomic per record and wavefront
+                    const float tot = wave_sum_to_last(wsum);
+                    if (lane == 63 && tot != 0.0f) atomicAdd(&a.weight[__float_as_uint(s_rec[3 * k + 2].y)], tot);
+                }
+                if constexpr (MARK) {
+                    const uint64_t m = __ballot(blended);
+                    if (m != 0ull && lane == __builtin_ctzll(m)) a.contrib[__float_as_uint(s_rec[3 * k + 2].y)] = 1;
+                }
+            };
+            // whether some pixel of the wavefront is still live
+            auto live = [&]() {
+                bool left = false;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) left = left || thr[p] < kInf;
+                return __ballot(left) != 0ull;
+            };
+            if constexpr (kBits) {
+                // only the records whose ellipse reaches this wavefront's cell, in
+                // order; the liveness test every 8 of them
+                int since = 0;
+                bool more = true;
+                for (int c = 0; c < cnt && more; c += 64) {
+                    const uint64_t word = s_bits[wave * kWords + c / 64];
+                    uint64_t bits = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(word >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)word);
+                    while (bits != 0ull) {
+                        blend(c + (int)__builtin_ctzll(bits));
+                        bits &= bits - 1ull;
+                        if (++since == 8) {
+                            since = 0;
+                            if (!live()) {
+                                more = false;
+                                break;
+                            }
+                        }
+                    }
+                }
             } else {
-                // several pixels: select-based updates, no branches or lane masks per pixel;
-                // groups of 8 records, leaving the batch once all of the thread's pixels stopped
+                // groups of 8 records, leaving the batch once no pixel of the wavefront is live
                 for (int k0 = 0; k0 < cnt; k0 += 8) {
                     const int kn = min(cnt, k0 + 8);
-                    for (int k = k0; k < kn; ++k) {
-                        const float4 g = s_rec[3 * k];
-                        const float4 h = s_rec[3 * k + 1];
-                        const float4 q = make_float4(g.z, g.w, h.x, h.y);
-                        const float cb = s_rec[3 * k + 2].x;
-                        const float dx = fx - g.x;
-                        const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
-                        const uint32_t pos = base + k - start + 1;
-                        bool blended = false;
-                        float wsum = 0.0f;
-#pragma unroll
-                        for (int p = 0; p < PPT; ++p) {
-                            // alpha below alpha_min enters as 0: the test then keeps T (>= t_min), w = 0
-                            const float e = exp2_at(q, A, B, fy[p] - g.y);
-                            const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
-                            const float al = alpha >= amin ? alpha : 0.0f;
-                            const float test = after(T[p], al);
-                            const bool ok = test >= thr[p];
-                            const float w = ok ? al * T[p] : 0.0f;
-                            C0[p] = fmaf(h.z, w, C0[p]);
-                            C1[p] = fmaf(h.w, w, C1[p]);
-                            C2[p] = fmaf(cb, w, C2[p]);
-                            if constexpr (LAST) last[p] = w > 0.0f ? pos : last[p];   // w >= alpha_min t_min > 0
-                            if constexpr (COUNT) stop[p] = (!ok && thr[p] < kInf) ? pos : stop[p];
-                            T[p] = ok ? test : T[p];
-                            thr[p] = ok ? thr[p] : kInf;
-                            if constexpr (MARK) blended = blended || w > 0.0f;
-                            if constexpr (WEIGHT) wsum += w;
-                        }
-                        if constexpr (WEIGHT) {
-                            // every lane is active here: one wave sum, one atomic per record and wave
-                            const float tot = wave_sum_to_last(wsum);
-                            if (lane_id() == 63 && tot != 0.0f)
-                                atomicAdd(&a.weight[__float_as_uint(s_rec[3 * k + 2].y)], tot);
-                        }
-                        if constexpr (MARK) {
-                            const uint64_t m = __ballot(blended);
-                            if (m != 0ull && lane_id() == __builtin_ctzll(m))
-                                a.contrib[__float_as_uint(s_rec[3 * k + 2].y)] = 1;
-                        }
-                    }
-                    bool left = false;
-#pragma unroll
-                    for (int p = 0; p < PPT; ++p) left = left || thr[p] < kInf;
-                    if (!left) {
-                        all_done = true;
-                        break;
-                    }
+                    for (int k = k0; k < kn; ++k) blend(k);
+                    if (!live()) break;
                 }
             }
         }
@@ -232,9 +321,12 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
 // turn).  Persistent schedule: a grid sized to the resident workgroups takes
 // items from a.order (longest tile list first, so the long lists do not start
 // last and leave the device idle at the end) through an atomic counter; every
-// workgroup leaves once the counter passes the item count.
+// workgroup leaves once the counter passes the item count.  With up to two
+// pixels per thread the register budget is held to eight wavefronts per SIMD
+// (where the LDS allows as many); four pixels need more registers than that.
 template <int TW, int TH, int BATCH, int PPT, int MODE, bool PERSIST>
-__global__ void __launch_bounds__(TW *TH / PPT) composite_kernel(CompArgs a) {
+__global__ void __launch_bounds__(TW *TH / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 4 ? 1 : 8)))
+composite_kernel(CompArgs a) {
     // per staged record three float4 at one address: centre (block-relative),
     // ka, kb | kc, log2 opacity, r, g | b, -, -, -
     __shared__ float4 s_rec[3 * BATCH];

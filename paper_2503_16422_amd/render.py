@@ -268,10 +268,10 @@ class Context:
         best = _lib.RenderCfg()
         ctypes.memmove(ctypes.byref(best), ctypes.byref(cfg), ctypes.sizeof(cfg))
         ms, vs = self._batch_structs(scenes, views)
-        res = (_lib.TuneResult * 64)()
+        res = (_lib.TuneResult * 128)()
         n = ctypes.c_int32()
         status = self.lib.fdgs_autotune(self.handle, ms, len(scenes), vs, len(views), int(views_per_launch),
-                                        int(repeats), ctypes.byref(best), res, 64, ctypes.byref(n),
+                                        int(repeats), ctypes.byref(best), res, 128, ctypes.byref(n),
                                         _stream(self.device))
         out = [dict(tile=(r.tile_w, r.tile_h), batch=r.batch, pixels_per_thread=r.pixels_per_thread,
                     schedule=r.schedule, ms=r.ms, identical=bool(r.identical)) for r in res[: n.value]]

@@ -125,7 +125,7 @@ def test_degenerate_gaussians_are_culled(ctx):
 
 # a4/a5 binning -------------------------------------------------------------------
 @pytest.mark.parametrize("cull", [1, 0])
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (32, 16), (32, 32)])
 def test_binning_bit_exact(ctx, cull, tile):
     """Without tile culling the lists are exactly the rectangle binning."""
     sc = inputs.tiny_scene(10_000, seed=0)
@@ -151,7 +151,7 @@ def test_binning_bit_exact(ctx, cull, tile):
 
 
 @pytest.mark.parametrize("cull", [1, 0])
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (32, 16), (32, 32)])
 def test_culled_binning_between_reached_and_rectangle(ctx, cull, tile):
     """With tile culling each list is the rectangle list minus Gaussians
     whose ellipse misses the tile, in the same order, and the image is the
@@ -253,7 +253,7 @@ def test_tile_and_batch_configs_give_identical_images(ctx):
     cam = inputs.look_at_camera(0.0, 3.0, 200, 150)
     model = to_dev(sc)
     base = None
-    for tile in ((16, 16), (8, 8), (32, 8)):
+    for tile in ((16, 16), (8, 8), (32, 8), (32, 16), (32, 32)):
         for batch in (64, 128, 256):
             for cull in (1, 0):
                 for ppt, tcull, sched in ((1, 1, 1), (2, 1, 0), (4, 1, 1), (2, 0, 1), (1, 0, 0)):
