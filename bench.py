@@ -76,14 +76,17 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel):
+def load_traffic(kernel, name=None):
     """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current sources of that kernel."""
+    were taken on the current sources of that kernel (and, given its full
+    name, on the same instantiation)."""
     p = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         d = json.load(f)
+    if name is not None and d.get("kernel") != name:
+        return None
     srcs = [os.path.join(ROOT, "paper_2503_16422_amd", "csrc", x) for x in d.get("sources", [])]
     if not srcs or not all(os.path.exists(x) for x in srcs) or source_sha(srcs) != d.get("source_sha"):
         return None
@@ -417,7 +420,7 @@ def main():
                  f"{'true' if cfg.schedule else 'false'}>")
         roof = {"bound": "alu", "kernel": kname, "achieved": round(comp_tflops, 3),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(comp_tflops / FP32_PEAK_TFLOPS, 4),
-                "traffic": load_traffic("composite")}
+                "traffic": load_traffic("composite", kname)}
     else:
         e = stages[dominant]
         roof = {"bound": "hbm", "kernel": dominant, "achieved": e["algorithmic_GBps"], "peak": HBM_PEAK_GBS,

@@ -33,6 +33,13 @@ __device__ __forceinline__ float exp2_at(float4 q, float A, float B, float dy) {
 __device__ __forceinline__ float gauss_exp2(float4 q, float dx, float dy) {
     return exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), dy);
 }
+// min(alpha_max, v) for v = exp2(...) >= +0 (or a NaN): non-negative floats
+// order as their bit patterns, so one unsigned minimum gives fminf's result
+// (alpha_max for +inf and for a NaN of either sign) without the operand
+// canonicalisation fminf needs.
+__device__ __forceinline__ float clamp_alpha(float v, uint32_t amax_bits) {
+    return __uint_as_float(min(__float_as_uint(v), amax_bits));
+}
 // Transmittance after blending alpha in front of T.
 __device__ __forceinline__ float after(float T, float alpha) { return fmaf(-alpha, T, T); }
 

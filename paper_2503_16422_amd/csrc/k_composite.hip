@@ -104,6 +104,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     // per-wavefront bitmaps of the batch's records that reach its cell (several
     // pixels per thread; a single-pixel thread branches per pixel instead)
     constexpr bool kBits = C::NW > 1 && PPT > 1;
+    const bool cull = a.rp.tile_cull != 0;   // without tile culling every record reaches every cell
     constexpr int kWords = BATCH / 64;
     __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
     const int n_tiles = a.rp.tiles_x * a.rp.tiles_y;
@@ -120,7 +121,8 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     const float fx = (float)(px - bx0) + 0.5f;
     const float ox = (float)bx0, oy = (float)by0;
     const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
-    const float amin = a.rp.alpha_min, amax = a.rp.alpha_max, tmin = a.rp.t_min;
+    const float amin = a.rp.alpha_min, tmin = a.rp.t_min;
+    const uint32_t amax_bits = __float_as_uint(a.rp.alpha_max);
     constexpr bool COUNT = MODE == kCount;
     constexpr bool LAST = MODE == kState || MODE == kCount;
     constexpr bool MARK = MODE == kMark;
@@ -164,12 +166,14 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 const uint32_t id = a.ids[base + k];
                 const Rec2D r = a.rec[id];
                 const float4 q = staged_conic(r);
-                if constexpr (kBits) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
+                if constexpr (kBits) {
+                    if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
+                }
                 s_rec[3 * k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
                 s_rec[3 * k + 1] = make_float4(q.z, q.w, r.c.x, r.c.y);
                 s_rec[3 * k + 2] = make_float4(r.c.z, __uint_as_float(id), 0.0f, 0.0f);
             }
-            if constexpr (kBits) {
+            if (kBits && cull) {
                 const int word = k0 / 64 + wave;
 #pragma unroll
                 for (int w = 0; w < C::NW; ++w) {
@@ -189,7 +193,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     const uint32_t pos = base + k - start + 1;
                     // one pixel: branch, so a wavefront skips the blend when no lane takes it
                     const float e = exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), fy[0] - g.y);
-                    const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
+                    const float alpha = clamp_alpha(__builtin_amdgcn_exp2f(e), amax_bits);
                     if (alpha < amin) continue;
                     const float test = after(T[0], alpha);
                     if (test < thr[0]) {
@@ -230,7 +234,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 for (int p = 0; p < PPT; ++p) {
                     // alpha below alpha_min enters as 0: the test then keeps T (>= t_min), w = 0
                     const float e = exp2_at(q, A, B, fy[p] - g.y);
-                    const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
+                    const float alpha = clamp_alpha(__builtin_amdgcn_exp2f(e), amax_bits);
                     const float al = alpha >= amin ? alpha : 0.0f;
                     const float test = after(T[p], al);
                     const bool ok = test >= thr[p];
@@ -262,7 +266,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 for (int p = 0; p < PPT; ++p) left = left || thr[p] < kInf;
                 return __ballot(left) != 0ull;
             };
-            if constexpr (kBits) {
+            if (kBits && cull) {
                 // only the records whose ellipse reaches this wavefront's cell, in
                 // order; the liveness test every 8 of them
                 int since = 0;

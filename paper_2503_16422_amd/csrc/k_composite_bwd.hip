@@ -52,6 +52,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     const float ox = (float)bx0, oy = (float)by0;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const float amin = a.rp.alpha_min, amax = a.rp.alpha_max;
+    const uint32_t amax_bits = __float_as_uint(amax);
     const int64_t plane = (int64_t)a.W * a.H;
     float fy[PPT], g0[PPT], g1[PPT], g2[PPT], T[PPT], S0[PPT], S1[PPT], S2[PPT], bgdot[PPT];
     uint32_t last[PPT];
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                 if (pos < last[p]) {
                     const float dy = fy[p] - c.y;
                     const float raw = __builtin_amdgcn_exp2f(exp2_at(q, A, B, dy));   // opacity x G
-                    const float alpha = fminf(amax, raw);
+                    const float alpha = clamp_alpha(raw, amax_bits);
                     if (alpha >= amin) {
                         hit = true;
                         const float4 col = s_rgb[k];
