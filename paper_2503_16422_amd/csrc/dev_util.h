@@ -9,6 +9,19 @@ namespace fdgs {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
+// XCD-aware item of block b in a grid of n blocks.  Workgroups go to the
+// eight XCDs (each with its own L2) round-robin by block index; here the
+// blocks of one XCD take one contiguous range of items, so that neighbouring
+// items -- which share cache lines of column-major histograms and of the runs
+// a radix pass scatters -- are handled under one L2 and their partial-line
+// writes merge there instead of reaching HBM separately.  A bijection of
+// [0, n): XCD x takes n / 8 items, one more when x < n % 8.
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
+    constexpr int64_t kXcds = 8;
+    const int64_t q = n / kXcds, r = n % kXcds, x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
+}
+
 // Inclusive sum over the 64 lanes of a wavefront.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_sum(T v) {

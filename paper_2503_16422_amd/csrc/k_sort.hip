@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, cons
     const int64_t n = count_of(n_dev, n_max);
     const uint32_t mask = (1u << bits) - 1u;
     h[threadIdx.x] = 0;
-    const int64_t base = (int64_t)blockIdx.x * (KPT * kNT) + (int64_t)wave_id() * (KPT * 64) + lane_id();
+    const int64_t c = xcd_item(blockIdx.x, gridDim.x);      // chunk of this block
+    const int64_t base = c * (KPT * kNT) + (int64_t)wave_id() * (KPT * 64) + lane_id();
     uint32_t k[KPT];
     if (base < n) {
 #pragma unroll
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, cons
         if (valid && __popcll(match & lt_mask) == cnt - 1) atomicAdd(&h[d], cnt);   // last lane of its group
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * gridDim.x + c] = h[threadIdx.x];   // rows of used digits
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts,
@@ -125,7 +126,8 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
     for (int k = 0; k < kRadix / 64; ++k) s_cnt[w][k * 64 + lane] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const int64_t bbase = (int64_t)blockIdx.x * CH;
+    const int64_t c = xcd_item(blockIdx.x, gridDim.x);      // chunk of this block
+    const int64_t bbase = c * CH;
     const int64_t wbase = bbase + (int64_t)w * (KPT * 64);
     uint32_t key[KPT], val[KPT], rank[KPT];
     // every load first (indices clamped to the last counted key), so that
@@ -156,10 +158,11 @@ __global__ void __launch_bounds__(kNT) downsweep_kernel(const uint32_t *keys, co
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
-    const int dd = threadIdx.x;                  // thread dd owns digit dd
+    const int dd = threadIdx.x;                  // thread dd owns digit dd (rows past mask are not kept)
+    const bool used = (uint32_t)dd <= mask;
     uint32_t tot;
-    const uint32_t gbase = block_exclusive_sum<kNT>(digit_total[dd], s_tmp, &tot) +
-                           hist[(int64_t)dd * hist_cols + (int64_t)blockIdx.x * hist_ratio];
+    const uint32_t gbase = block_exclusive_sum<kNT>(used ? digit_total[dd] : 0u, s_tmp, &tot) +
+                           (used ? hist[(int64_t)dd * hist_cols + c * hist_ratio] : 0u);
     uint32_t dcount = 0;
 #pragma unroll
     for (int k = 0; k < kNW; ++k) dcount += s_cnt[k][dd];
@@ -279,10 +282,11 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
     const int64_t n_inst_all = *n_inst_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_inst_all > capacity) atomicOr(overflow, 1);
     const int64_t n_inst = min(n_inst_all, capacity);
-    const int64_t e_lo = (int64_t)blockIdx.x * kDupE;
+    const int64_t wdx = xcd_item(blockIdx.x, gridDim.x);    // window of this block
+    const int64_t e_lo = wdx * kDupE;
     if (e_lo >= n_inst || n_vis <= 0) {                // uniform
-        if (hist) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = 0u;   // empty window
-        return;
+        if (hist && (int)threadIdx.x < (1 << hist_bits)) hist[(int64_t)threadIdx.x * gridDim.x + wdx] = 0u;
+        return;                                        // an empty window
     }
     const int64_t e_hi = min(e_lo + (int64_t)kDupE, n_inst);
     const int t = threadIdx.x;
@@ -378,7 +382,7 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
         const uint32_t dmask = (1u << hist_bits) - 1u;
         for (int i = t; i < len; i += kDupNT) atomicAdd(&s_h[s_key[i] & dmask], 1u);
         __syncthreads();
-        hist[(int64_t)t * gridDim.x + blockIdx.x] = s_h[t];
+        if (t < (1 << hist_bits)) hist[(int64_t)t * gridDim.x + wdx] = s_h[t];
     }
 }
 
@@ -474,7 +478,7 @@ static void sort_pass(const uint32_t *src_k, const uint32_t *src_v, uint32_t *ds
                            bits, hist);
         hist_cols = nb;
     }
-    hipLaunchKernelGGL(rowscan_kernel, dim3(kRadix), dim3(1024), 0, s, hist, hist_cols, digit_total);
+    hipLaunchKernelGGL(rowscan_kernel, dim3(1u << bits), dim3(1024), 0, s, hist, hist_cols, digit_total);
     hipLaunchKernelGGL((downsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, src_v, dst_k, dst_v,
                        n_dev, n_max, shift, bits, (const uint32_t *)hist, hist_cols, (int)(hist_cols / nb),
                        (const uint32_t *)digit_total);
