@@ -192,6 +192,11 @@ def cpu_baseline(scene, jobs):
             "cpu": platform.processor() or platform.machine()}
 
 
+# tile shapes and LDS batches tried for the fwd+bwd loop (the forward autotuner
+# times forwards only; here the adjoint decides as much)
+FWD_BWD_TILES = ((16, 16, 128), (16, 16, 256), (32, 16, 256), (32, 32, 256))
+
+
 def fwd_bwd(ctx, steps, warmup):
     import numpy as np
     import torch
@@ -204,38 +209,51 @@ def fwd_bwd(ctx, steps, warmup):
     views = [(int(c), float(t)) for c, t in zip(rng.choice(20, 4, replace=False), rng.uniform(0, 1, 4))]
     model = GaussianModel.from_scene(sc, "cuda:0")
     tmodel = GaussianModel.from_scene(tgt, "cuda:0")
-    cfg = _lib.default_cfg()
-    targets = [ctx.render(tmodel, cams[c], t, cfg)[0].clone() for c, t in views]
+    targets = [ctx.render(tmodel, cams[c], t, _lib.default_cfg())[0].clone() for c, t in views]
     grads = {k: torch.zeros_like(getattr(model, k)) for k in GaussianModel.FIELDS}
     states = [None] * 4
 
-    def step():
+    def step(cfg):
         for g in grads.values():
             g.zero_()
-        loss = 0.0
         for v, (c, t) in enumerate(views):
             rgb, _, states[v] = ctx.render(model, cams[c], t, cfg, keep_state=states[v] or True)
             dL = rgb - targets[v]
             ctx.backward(states[v], dL, model, grads)
-        return loss
 
-    for _ in range(warmup):
-        step()
-    sync()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    sync()
-    dt = time.perf_counter() - t0
+    def release():
+        for v, st in enumerate(states):
+            if st is not None:
+                ctx.release(st)
+            states[v] = None
+
+    def timed(cfg, n, nw):
+        for _ in range(nw):
+            step(cfg)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            step(cfg)
+        sync()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    sweep = {}
+    for tw, th, b in FWD_BWD_TILES:
+        cfg = _lib.default_cfg(tile_w=tw, tile_h=th, batch=b)
+        sweep[f"{tw}x{th}/b{b}"] = round(timed(cfg, 4, 2), 3)
+        release()
+    best = min(sweep, key=sweep.get)
+    tw, th = (int(x) for x in best.split("/")[0].split("x"))
+    cfg = _lib.default_cfg(tile_w=tw, tile_h=th, batch=int(best.split("/b")[1]))
+    ms = timed(cfg, steps, warmup)
     ctx.profile(True)
     for _ in range(3):
-        step()
+        step(cfg)
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
     stage_ms = {k: round(v / 3, 4) for k, v in prof["ms"].items() if v > 0}
-    for s in states:
-        ctx.release(s)
-    return dt * 1e3 / steps, views, stage_ms
+    release()
+    return ms, views, stage_ms, {"chosen": best, "sweep_ms_per_iter": sweep}
 
 
 def batched(ctx, steps=3):
@@ -344,8 +362,8 @@ def main():
         sync()
         del a, b
     if args.fwd_bwd_only:
-        ms_iter, views, fb_stages = fwd_bwd(ctx, args.steps, args.warmup)
-        log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter; stages {json.dumps(fb_stages)}")
+        ms_iter, views, fb_stages, fb_tiles = fwd_bwd(ctx, args.steps, args.warmup)
+        log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter; tiles {fb_tiles}; stages {json.dumps(fb_stages)}")
         return
     W, H = 1352, 1014
     cams = inputs.arc_cameras(20, 4.0, W, H)
@@ -504,12 +522,13 @@ def main():
 
         # ---- forward + backward ------------------------------------------------------
         log("[bench] fwd+bwd: 500k Gaussians, 4 views")
-        ms_iter, views, fb_stages = fwd_bwd(ctx, 20, 5)
+        ms_iter, views, fb_stages, fb_tiles = fwd_bwd(ctx, 20, 5)
         extra["fwd_bwd_ms_per_iter"] = round(ms_iter, 3)
         extra["fwd_bwd_stage_ms_per_iter"] = fb_stages
         extra["fwd_bwd_config"] = {"gaussians": 500_000, "views": views, "resolution": [W, H],
-                                   "loss": "0.5*sum((I-I*)^2), targets rendered from a second seed"}
-        log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter")
+                                   "loss": "0.5*sum((I-I*)^2), targets rendered from a second seed",
+                                   "tiles": fb_tiles}
+        log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter ({fb_tiles})")
 
     cpu = None
     if not args.no_cpu_baseline and not args.headline_only:

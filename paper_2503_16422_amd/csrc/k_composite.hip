@@ -17,7 +17,6 @@
 #include <algorithm>
 
 #include "dev_composite.h"
-#include "dev_cull.h"
 #include "dev_util.h"
 #include "fdgs_internal.h"
 
@@ -44,46 +43,6 @@ struct CompArgs {
     uint8_t *contrib;            // kMark: per processed entry, set to 1 when blended
     float *weight;               // kWeight: per processed entry, += sum of alpha T
 };
-
-// Thread layout: each wavefront owns a CW x CH block ("cell") of the tile and
-// each of its threads PPT consecutive pixels of one column of the cell
-// (TW x TH / PPT threads); the column's dx terms and the LDS reads of a record
-// are shared by the thread's PPT pixels.  Cells are 16 pixels wide where the
-// tile allows, so several wavefronts split a tile into blocks that a record's
-// footprint often misses: with several pixels per thread, the staging marks
-// in one bitmap per wavefront the records whose ellipse reaches its cell, and
-// the wavefront walks only those (a scalar bit scan per record).
-template <int TW, int TH, int PPT>
-struct Cells {
-    static constexpr int CW = (TW >= 16 && TH >= 4 * PPT) ? 16 : TW;
-    static constexpr int CH = 64 * PPT / CW;
-    static constexpr int CX = TW / CW;
-    static constexpr int NW = CX * (TH / CH);
-    static_assert(TW % CW == 0 && TH % CH == 0 && NW * 64 * PPT == TW * TH, "whole cells per tile");
-};
-
-// Bit w set when the record's footprint ellipse reaches a pixel of wavefront
-// w's cell of the tile with origin (x0, y0) (every bit when tile culling is
-// off, or the ellipse is not usable for it).  One column span per band of
-// cell rows, then a range test per cell of the band.
-template <int TW, int TH, int PPT>
-__device__ __forceinline__ uint32_t reached_cells(const Rec2D &r, const RenderParams &rp, int x0, int y0) {
-    using C = Cells<TW, TH, PPT>;
-    const CullEllipse e = cull_ellipse(r, rp);
-    uint32_t m = 0;
-#pragma unroll 1
-    for (int band = 0; band < C::NW / C::CX; ++band) {
-        const int r0 = y0 + band * C::CH;
-        int p0 = x0, p1 = x0 + TW - 1;
-        if (!ellipse_band_columns(e, r0, r0 + C::CH - 1, x0, x0 + TW - 1, &p0, &p1)) continue;
-#pragma unroll
-        for (int cx = 0; cx < C::CX; ++cx) {
-            const int c0 = x0 + cx * C::CW;
-            if (p0 <= c0 + C::CW - 1 && p1 >= c0) m |= 1u << (band * C::CX + cx);
-        }
-    }
-    return m;
-}
 
 // What a compositor instance records beyond colour and transmittance.
 enum CompMode {

@@ -30,13 +30,22 @@ struct BwdArgs {
 //   dL/dc_i = a_i T_i g
 //   dL/da_i = T_i c_i.g - (S.g + T_final bg.g) / (1 - a_i)
 // then a_i = min(a_max, o_i G_i) -> (o_i, conic, centre).  A thread owns PPT
-// pixels of a column (as in the forward) and adds their terms before the
-// per-Gaussian sums are reduced over each row of 16 lanes (DPP) and added into
-// the tile's LDS accumulators by one lane per row; one global add per value
-// and Gaussian leaves the tile after each batch.
+// pixels of a column of its wavefront's cell (the forward's layout) and adds
+// their terms before the per-Gaussian sums are reduced over each row of 16
+// lanes (DPP) and added into the tile's LDS accumulators by one lane per row;
+// one global add per value and Gaussian leaves the tile after each batch.
+// With several cells per tile (and tile culling on) a wavefront walks only the
+// records whose footprint ellipse reaches its cell: the others have alpha
+// below alpha_min at every one of its pixels and contribute nothing.
 template <int TW, int TH, int BATCH, int PPT>
 __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) {
     constexpr int NT = TW * TH / PPT;
+    using C = Cells<TW, TH, PPT>;
+    // per-wavefront bitmaps of the batch's records that reach its cell (as in the forward)
+    constexpr bool kBits = C::NW > 1;
+    constexpr int kWords = BATCH / 64;
+    __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
+    const bool cull = a.rp.tile_cull != 0;
     __shared__ float2 s_xy[BATCH];
     __shared__ float4 s_cn[BATCH];    // staged conic and opacity, as in the forward
     __shared__ float4 s_rgb[BATCH];
@@ -45,12 +54,13 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     __shared__ float s_acc[BATCH * 9]; // per-Gaussian gradient sums of the tile
     const int tile = blockIdx.x;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
-    const int lx = threadIdx.x % TW, ly0 = (threadIdx.x / TW) * PPT;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = lane_id();
+    const int lx = (wave % C::CX) * C::CW + lane % C::CW, ly0 = (wave / C::CX) * C::CH + (lane / C::CW) * PPT;
     const int px = tx * TW + lx, py0 = ty * TH + ly0;
     const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;   // as in the forward
     const float fx = (float)(px - bx0) + 0.5f;
     const float ox = (float)bx0, oy = (float)by0;
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t start = a.ranges[2 * tile];
     const float amin = a.rp.alpha_min, amax = a.rp.alpha_max;
     const uint32_t amax_bits = __float_as_uint(amax);
     const int64_t plane = (int64_t)a.W * a.H;
@@ -83,23 +93,38 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     atomicMax(&s_max, my_max);
     __syncthreads();
     const uint32_t walk_end = start + s_max;
-    const int lane = lane_id();
     for (int j = threadIdx.x; j < BATCH * 9; j += NT) s_acc[j] = 0.0f;
     for (int64_t top = (int64_t)walk_end; top > (int64_t)start; top -= BATCH) {
         const uint32_t lo = (uint32_t)max((int64_t)start, top - BATCH);
         const int cnt = (int)(top - lo);
         __syncthreads();
-        for (int k = threadIdx.x; k < cnt; k += NT) {
-            const uint32_t id = a.ids[lo + k];
-            const Rec2D r = a.rec[id];
-            s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
-            s_cn[k] = staged_conic(r);
-            s_rgb[k] = r.c;
-            s_id[k] = id;
-            s_io[k] = 1.0f / r.b.w;
+        for (int k0 = 0; k0 < cnt; k0 += NT) {
+            const int k = k0 + (int)threadIdx.x;
+            uint32_t cells = 0u;
+            if (k < cnt) {
+                const uint32_t id = a.ids[lo + k];
+                const Rec2D r = a.rec[id];
+                s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
+                s_cn[k] = staged_conic(r);
+                s_rgb[k] = r.c;
+                s_id[k] = id;
+                s_io[k] = 1.0f / r.b.w;
+                if constexpr (kBits) {
+                    if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
+                }
+            }
+            if (kBits && cull) {
+                const int word = k0 / 64 + wave;
+#pragma unroll
+                for (int w = 0; w < C::NW; ++w) {
+                    const uint64_t m = __ballot((cells >> w) & 1u);
+                    if (lane == 0 && word < kWords) s_bits[w * kWords + word] = m;
+                }
+            }
         }
         __syncthreads();
-        for (int k = cnt - 1; k >= 0; --k) {
+        // one record, back to front; every lane of the wavefront takes part
+        auto grad_record = [&](int k) {
             const uint32_t pos = lo + k - start;   // position in the tile list
             const float2 c = s_xy[k];
             const float4 q = s_cn[k];
@@ -167,6 +192,21 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                     atomicAdd(acc + 8, dbl);
                 }
             }
+        };
+        if (kBits && cull) {
+            // only the records whose ellipse reaches this wavefront's cell
+            for (int c = (cnt - 1) / 64; c >= 0; --c) {
+                const uint64_t word = s_bits[wave * kWords + c];
+                uint64_t bits = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(word >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)word);
+                while (bits != 0ull) {
+                    const int b = 63 - __builtin_clzll(bits);
+                    bits &= ~(1ull << b);
+                    grad_record(c * 64 + b);
+                }
+            }
+        } else {
+            for (int k = cnt - 1; k >= 0; --k) grad_record(k);
         }
         __syncthreads();
         // one global add per (Gaussian, value) for the whole tile
