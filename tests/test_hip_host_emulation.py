@@ -50,3 +50,8 @@ def test_tile_binning_kernels_on_host(tmp_path):
     FDGS_HOST_EMU_FULL=1 also above 2^20 instances, where the emission writes
     the sort's first-digit histogram (several minutes in the emulation)."""
     run_on_host(tmp_path, "k_sort.hip", "sort_check.cpp", *(["full"] if os.environ.get("FDGS_HOST_EMU_FULL") else []))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_xcd_block_order_is_a_bijection(tmp_path):
+    run_on_host(tmp_path, "k_sort.hip", "xcd_check.cpp")
