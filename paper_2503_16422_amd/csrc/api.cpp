@@ -92,6 +92,7 @@ struct fdgs_state {
     // per processed Gaussian
     Buf rec, depth_key, rect, tiles, visible, vis_pos, order_k, order_v, order_k2, order_v2, offsets, view_of;
     Buf bucket;        // depth buckets: counts, cursors, starts, key range
+    Buf vis_count;     // visible entries per preprocess workgroup
     // per instance
     Buf tkeys, tids, tkeys2, tids2;
     // per tile / pixel
@@ -117,7 +118,7 @@ struct fdgs_state {
 
     void free_all() {
         for (Buf *b : {&rec, &depth_key, &rect, &tiles, &visible, &vis_pos, &order_k, &order_v, &order_k2,
-                       &order_v2, &offsets, &view_of, &bucket, &tkeys, &tids, &tkeys2, &tids2, &ranges, &sched,
+                       &order_v2, &offsets, &view_of, &bucket, &vis_count, &tkeys, &tids, &tkeys2, &tids2, &ranges, &sched,
                        &T_final, &n_contrib, &counts, &g2d, &scratch})
             release(*b);
     }
@@ -549,8 +550,9 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     int64_t *counts = S->counts.as<int64_t>();
     uint32_t *view_of = V > 1 ? S->view_of.as<uint32_t>() : nullptr;
 
+    HIP_TRY(ensure(S->vis_count, sizeof(uint32_t) * (size_t)((n_total + kPreprocessBlock - 1) / kPreprocessBlock)));
     PreprocOut po{S->rec.as<Rec2D>(), S->depth_key.as<uint64_t>(), S->rect.as<int32_t>(),
-                  S->tiles.as<uint32_t>(), S->visible.as<uint8_t>(), view_of};
+                  S->tiles.as<uint32_t>(), S->visible.as<uint8_t>(), view_of, S->vis_count.as<uint32_t>()};
     {
         StageTimer tm(ctx, FDGS_STAGE_PREPROCESS, stream);
         HIP_TRY(launch_preprocess(one, table, V, n_dev, n_total, rp, po, stream));
@@ -561,7 +563,8 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
         HIP_TRY(compact_visible(S->visible.as<uint8_t>(), S->depth_key.as<uint64_t>(), n_dev, n_max, counts + 0,
                                 S->order_k.as<uint32_t>(), S->order_v.as<uint32_t>(),
                                 need_state ? S->vis_pos.as<uint32_t>() : nullptr, bwork, by_buckets ? 2 * n_buckets : 0,
-                                by_buckets ? bwork + 3 * n_buckets + 1 : nullptr, S->scratch.p, stream));
+                                by_buckets ? bwork + 3 * n_buckets + 1 : nullptr, S->scratch.p, stream,
+                                S->vis_count.as<uint32_t>()));
     }
     uint32_t *ov = nullptr;
     {

@@ -31,7 +31,10 @@ struct PreprocOut {
     uint32_t *tiles;     // [P] tiles touched (0 = not visible)
     uint8_t *visible;    // [P]
     uint32_t *view_of;   // [P] view of each entry (written when V > 1)
+    uint32_t *vis_count; // [ceil(P / kPreprocessBlock)] visible entries per workgroup, or NULL
 };
+// Entries per preprocess workgroup (its visible counts feed the compaction's scan).
+constexpr int kPreprocessBlock = 256;
 // V == 1: `one` is passed by value and n_dev may hold the device count.
 // V > 1: `table` is a device array of V views with host-known counts.
 hipError_t launch_preprocess(const ViewDesc *one, const ViewDesc *table, int32_t V, const int64_t *n_dev,
@@ -60,10 +63,13 @@ hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t 
 // Visible entries in order -> keys32 = float32 bits of their depth, vals = position (and, when asc is
 // not NULL, asc = position too: a copy the depth sort does not overwrite); *total = count.  Before the
 // entries are written, clear[0..n_clear) is zeroed and range (when not NULL) receives the [min, max]
-// of the keys.
+// of the keys.  vis_count (may be NULL): the preprocess's visible count per workgroup of
+// kPreprocessBlock entries (ceil(n_max / kPreprocessBlock) of them), which replaces the scan's
+// first pass over the flags.
 hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
                            int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, uint32_t *clear,
-                           int64_t n_clear, uint32_t *range, void *scratch, hipStream_t s);
+                           int64_t n_clear, uint32_t *range, void *scratch, hipStream_t s,
+                           const uint32_t *vis_count = nullptr);
 
 // Depth order of one view's visible entries by bucketing and per-bucket sorts: out[0..n_vis) = the
 // positions (vals) ordered by (depth_key[pos], pos).  work holds bucket_scratch_words(n_max) words:

@@ -20,7 +20,7 @@
 namespace fdgs {
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kPreprocessBlock;
 
 __global__ void __launch_bounds__(kBlock) slice_kernel(KModel m, double t, const uint32_t *idx,
                                                        int64_t count, float *mean3, float *cov3,
@@ -167,6 +167,10 @@ __global__ void __launch_bounds__(kBlock) preprocess_kernel(PreArgs a) {
     }
     __syncthreads();
     if (j < P) a.out.tiles[j] = s_cnt[t];
+    if (a.out.vis_count) {                          // uniform
+        const int nv = __syncthreads_count(vis);
+        if (t == 0) a.out.vis_count[blockIdx.x] = (uint32_t)nv;
+    }
 }
 
 struct MaskKArgs {

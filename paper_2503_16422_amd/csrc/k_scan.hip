@@ -85,9 +85,12 @@ __global__ void __launch_bounds__(kNT) reduce_kernel(Load ld, const int64_t *n_d
 
 // Exclusive scan of nb block sums by one block; writes the grand total.
 // Optionally clears n_clear words and resets a [min, max] key range to
-// (all ones, 0) for the kernel that follows.
+// (all ones, 0) for the kernel that follows.  With group_in, block sum j is
+// instead the sum of group_in[j * group .. j * group + group) (entries past
+// n_in count as 0), written to partial[j] before the scan.
 __global__ void __launch_bounds__(kTopNT) top_scan_kernel(uint64_t *partial, int64_t nb, int64_t *total,
-                                                          uint32_t *clear, int64_t n_clear, uint32_t *range) {
+                                                          uint32_t *clear, int64_t n_clear, uint32_t *range,
+                                                          const uint32_t *group_in, int64_t n_in, int group) {
     __shared__ uint64_t tmp[kTopNT / 64 + 1];
     for (int64_t i = threadIdx.x; i < n_clear; i += kTopNT) clear[i] = 0u;
     if (range && threadIdx.x == 0) {
@@ -97,7 +100,17 @@ __global__ void __launch_bounds__(kTopNT) top_scan_kernel(uint64_t *partial, int
     uint64_t carry = 0;
     for (int64_t start = 0; start < nb; start += kTopNT) {
         const int64_t j = start + threadIdx.x;
-        const uint64_t v = j < nb ? partial[j] : 0;
+        uint64_t v = 0;
+        if (j < nb) {
+            if (group_in) {
+                for (int g = 0; g < group; ++g) {
+                    const int64_t i = j * group + g;
+                    if (i < n_in) v += group_in[i];
+                }
+            } else {
+                v = partial[j];
+            }
+        }
         uint64_t tot;
         const uint64_t ex = block_exclusive_sum<kTopNT>(v, tmp, &tot);
         if (j < nb) partial[j] = carry + ex;
@@ -134,12 +147,13 @@ hipError_t scan_impl(Load ld, Out *out, const int64_t *n_dev, int64_t n_max, int
     if (nb == 0) {
         // still define the total
         hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, (int64_t)0, total,
-                           (uint32_t *)nullptr, (int64_t)0, (uint32_t *)nullptr);
+                           (uint32_t *)nullptr, (int64_t)0, (uint32_t *)nullptr,
+                           (const uint32_t *)nullptr, (int64_t)0, 1);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((reduce_kernel<Load>), dim3((unsigned)nb), dim3(kNT), 0, s, ld, n_dev, n_max, partial);
     hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total, (uint32_t *)nullptr,
-                       (int64_t)0, (uint32_t *)nullptr);
+                       (int64_t)0, (uint32_t *)nullptr, (const uint32_t *)nullptr, (int64_t)0, 1);
     hipLaunchKernelGGL((downsweep_kernel<Load, Out>), dim3((unsigned)nb), dim3(kNT), 0, s, ld, n_dev,
                        n_max, (const uint64_t *)partial, out);
     return hipGetLastError();
@@ -274,13 +288,23 @@ hipError_t scan_u32_to_u64(const uint32_t *in, const uint32_t *gather, uint64_t 
 
 hipError_t compact_visible(const uint8_t *visible, const uint64_t *depth_key, const int64_t *n_dev, int64_t n_max,
                            int64_t *total, uint32_t *keys32, uint32_t *vals, uint32_t *asc, uint32_t *clear,
-                           int64_t n_clear, uint32_t *range, void *scratch, hipStream_t s) {
+                           int64_t n_clear, uint32_t *range, void *scratch, hipStream_t s,
+                           const uint32_t *vis_count) {
+    static_assert(kChunk % kPreprocessBlock == 0, "whole preprocess workgroups per scan chunk");
     const int64_t nb = (n_max + kChunk - 1) / kChunk;
     uint64_t *partial = static_cast<uint64_t *>(scratch);
-    if (nb > 0)
-        hipLaunchKernelGGL((reduce_kernel<LoadU8>), dim3((unsigned)nb), dim3(kNT), 0, s, LoadU8{visible}, n_dev, n_max,
-                           partial);
-    hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total, clear, n_clear, range);
+    if (vis_count) {
+        // the preprocess counted each workgroup's visible entries: sum them per chunk in the scan
+        const int64_t n_in = (n_max + kPreprocessBlock - 1) / kPreprocessBlock;
+        hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total, clear, n_clear, range,
+                           vis_count, n_in, kChunk / kPreprocessBlock);
+    } else {
+        if (nb > 0)
+            hipLaunchKernelGGL((reduce_kernel<LoadU8>), dim3((unsigned)nb), dim3(kNT), 0, s, LoadU8{visible}, n_dev,
+                               n_max, partial);
+        hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, total, clear, n_clear, range,
+                           (const uint32_t *)nullptr, (int64_t)0, 1);
+    }
     if (nb > 0)
         hipLaunchKernelGGL(compact_visible_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, visible, depth_key, n_dev,
                            n_max, (const uint64_t *)partial, keys32, vals, asc, range);
@@ -295,7 +319,7 @@ hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t 
     if (nb > 0)
         hipLaunchKernelGGL(bits_count_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, n, nw, partial);
     hipLaunchKernelGGL(top_scan_kernel, dim3(1), dim3(kTopNT), 0, s, partial, nb, count, (uint32_t *)nullptr,
-                       (int64_t)0, (uint32_t *)nullptr);
+                       (int64_t)0, (uint32_t *)nullptr, (const uint32_t *)nullptr, (int64_t)0, 1);
     if (nb > 0)
         hipLaunchKernelGGL(bits_compact_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, n,
                            (const uint64_t *)partial, idx);

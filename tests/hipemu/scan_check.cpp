@@ -62,6 +62,17 @@ int main() {
         if (j > 0 && (range[0] != kmin || range[1] != kmax)) return fail("key range");
         for (uint32_t x : clear)
             if (x) return fail("clear");
+        // the same compaction from per-workgroup visible counts (as the preprocess writes them)
+        std::vector<uint32_t> vc((n_max + kPreprocessBlock - 1) / kPreprocessBlock, 0);
+        for (int64_t i = 0; i < n; ++i) vc[i / kPreprocessBlock] += vis[i] ? 1u : 0u;
+        std::vector<uint32_t> keys2(n_max, 9), vals2(n_max, 9), asc2(n_max, 9), clear2(100, 5), range2(2, 5);
+        int64_t nvis2 = -1;
+        compact_visible(vis.data(), dk.data(), &nd, n_max, &nvis2, keys2.data(), vals2.data(), asc2.data(),
+                        clear2.data(), 100, range2.data(), scratch.data(), nullptr, vc.data());
+        if (nvis2 != nvis || range2 != range || clear2 != clear) return fail("compaction from workgroup counts");
+        for (int64_t i = 0; i < nvis; ++i)
+            if (keys2[i] != keys[i] || vals2[i] != vals[i] || asc2[i] != asc[i])
+                return fail("compaction order from workgroup counts");
         // active-set bits -> ascending indices
         std::vector<uint32_t> bits((n_max + 31) / 32);
         for (auto &w : bits) w = (uint32_t)rng();
