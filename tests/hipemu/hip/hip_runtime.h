@@ -28,7 +28,7 @@
 #define HIP_SYMBOL(x) (&x)
 
 typedef int hipError_t;
-enum { hipSuccess = 0 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
 typedef void *hipStream_t;
 inline hipError_t hipGetLastError() { return hipSuccess; }
 
