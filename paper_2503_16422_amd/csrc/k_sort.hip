@@ -457,8 +457,12 @@ constexpr int64_t kRangesSearchAbove = 2048;
 
 }  // namespace
 
-// Keys per thread: small sorts use short chunks so that more blocks run.
-inline int sort_kpt(int64_t n_max) { return n_max <= (int64_t(1) << 20) ? 4 : 16; }
+// Keys per thread: small sorts use short chunks so that more blocks run; up to
+// 2^21 keys the chunk equals the emission window (2048), so a tile sort of
+// that size takes its first histogram from the emission.
+inline int sort_kpt(int64_t n_max) {
+    return n_max <= (int64_t(1) << 19) ? 4 : n_max <= (int64_t(1) << 21) ? 8 : 16;
+}
 
 size_t sort_scratch_bytes(int64_t n_max, int64_t hist_cols) {
     const int64_t chunk = (int64_t)sort_kpt(n_max) * kNT;
@@ -514,6 +518,8 @@ hipError_t radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, ui
         const int64_t given = p == 0 ? first_hist_cols : 0;
         if (kpt == 4)
             sort_pass<4>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, given, s);
+        else if (kpt == 8)
+            sort_pass<8>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, given, s);
         else
             sort_pass<16>(src_k, src_v, dst_k, dst_v, n_dev, n_max, shift, bits, hist, digit_total, nb, given, s);
         uint32_t *tk = src_k, *tv = src_v;
