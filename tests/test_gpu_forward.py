@@ -239,6 +239,29 @@ def test_long_tile_lists_take_the_searched_ranges(ctx):
     ctx.release(st)
 
 
+@pytest.mark.parametrize("grow", [1.6, 2.3])
+def test_many_instances_bin_exactly(ctx, grow):
+    """8M and 19M instances (8x8 tiles, no tile culling): the tile sort takes
+    4096 keys per block, two emission windows per block writing its first
+    histogram, over thousands of histogram columns; lists and ranges must
+    match the oracle bit for bit."""
+    sc = inputs.tiny_scene(40_000, seed=8)
+    sc.log_scale[:3] += grow
+    sc.log_scale[3] += 3.0
+    cam = inputs.look_at_camera(10.0, 3.0, 320, 240)
+    cfg = _lib.default_cfg(tile_w=8, tile_h=8, tile_cull=0)
+    _, _, st = ctx.render(to_dev(sc), cam, 0.5, cfg, keep_state=True)
+    b = ctx.binning(st)
+    torch.cuda.synchronize()
+    pre = oc.prepare(sc.arrays(), cam, 0.5, oracle_settings(cfg))
+    ids, _, ranges = obin.bin_gaussians(pre.rect, pre.depth, pre.visible, 320, 240, 8, 8)
+    assert ids.size > (1 << 21) if grow < 2 else ids.size > 4096 * 4096
+    assert b["n_inst"] == ids.size
+    assert np.array_equal(b["sorted_ids"].cpu().numpy().astype(np.uint32), ids)
+    assert_same_ranges(b["tile_ranges"].cpu().numpy().astype(np.uint32), ranges)
+    ctx.release(st)
+
+
 def assert_same_ranges(got, ref):
     """Non-empty tiles must match exactly; an empty tile may be any [s, s)."""
     nonempty = ref[:, 1] > ref[:, 0]
