@@ -390,6 +390,7 @@ def main():
         c, f = frame_schedule(k * 13, len(cams), len(frames))
         idx, cnt = masks[frame_window[f]]
         tune_views.append((0, cams[c], float(frames[f]), idx, int(cnt.item())))
+    refine = {}
     if args.config:
         tw, th, b, p, sc = (int(x) for x in args.config.split(","))
         tuned, sweep = dict(tile_w=tw, tile_h=th, batch=b, pixels_per_thread=p, schedule=sc), []
@@ -397,6 +398,19 @@ def main():
         best, sweep = ctx.autotune([model], tune_views, _lib.default_cfg(), views_per_launch=1, repeats=2)
         tuned = dict(tile_w=best.tile_w, tile_h=best.tile_h, batch=best.batch,
                      pixels_per_thread=best.pixels_per_thread, schedule=best.schedule)
+        # the sweep's three fastest, timed again the way the benchmark loop runs
+        # (fixed capacity, 100 frames), so that near-ties are settled on the loop itself
+        for r in sorted(sweep, key=lambda r: r["ms"])[:3]:
+            cand = dict(tile_w=r["tile"][0], tile_h=r["tile"][1], batch=r["batch"],
+                        pixels_per_thread=r["pixels_per_thread"], schedule=r["schedule"])
+            n_inst = max_instances(ctx, model, cams, frames, masks, frame_window, _lib.default_cfg(**cand), 110, 0)
+            cfg_c = _lib.default_cfg(instance_capacity=int(n_inst * 1.05) + 4096, **cand)
+            f_c, _ = timed_fps(ctx, model, cams, frames, masks, frame_window, cfg_c, 100, 10, out)
+            refine[tuple(cand.values())] = f_c
+            if f_c >= max(refine.values()):
+                tuned = cand
+        log(f"[bench] autotune refinement (frames/s over 100 frames): "
+            f"{ {'/'.join(str(x) for x in k): round(v, 1) for k, v in refine.items()} }")
     log(f"[bench] autotuned {tuned}")
     worst = max_instances(ctx, model, cams, frames, masks, frame_window, _lib.default_cfg(**tuned), K + Wu, 0)
     log(f"[bench] max instances over the timed frames {worst}")
@@ -550,6 +564,7 @@ def main():
                                "1352x1014, 20 cameras x 300 timestamps, keyframe masks every 10 frames "
                                "(temporal and tile predicate)",
                    "autotuned": tuned, "default_config_fps": round(fps_default, 2),
+                   "autotune_refinement_fps": {"/".join(str(x) for x in k): round(v, 1) for k, v in refine.items()},
                    "autotune_sweep_ms_per_frame": {
                        f"{r['tile'][0]}x{r['tile'][1]}/b{r['batch']}/p{r['pixels_per_thread']}/s{r['schedule']}":
                        round(r["ms"] / len(tune_views), 4) for r in sweep},
