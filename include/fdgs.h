@@ -109,7 +109,8 @@ typedef struct {
 typedef struct {
     int32_t tile_w, tile_h;     /* one of 8x8, 16x16, 32x8, 32x16,
                                    32x32                         [16x16] */
-    int32_t batch;              /* Gaussians staged in LDS: 64/128/256   [128] */
+    int32_t batch;              /* Gaussians staged in LDS: 64/128/256
+                                   (also 512/1024 with 32x32 tiles) [128] */
     int32_t pixels_per_thread;  /* 1, 2 or 4 pixels of a column per thread in
                                    the forward compositor; 8x8 tiles always
                                    use 1; 0 picks the default              [0] */
@@ -291,9 +292,9 @@ FDGS_API fdgs_status fdgs_render_batch(fdgs_ctx *ctx, const fdgs_model *scenes, 
 
 /*
  * Autotuner: renders the batch with every tile shape (8x8, 16x16, 32x8,
- * 32x16, 32x32), LDS batch (64, 128, 256), pixels-per-thread choice (1, 2, 4;
- * 1 only for 8x8) and compositor schedule (1, 0): 78 configurations, each
- * timed with HIP
+ * 32x16, 32x32), LDS batch (64, 128, 256; also 512 and 1024 for 32x32),
+ * pixels-per-thread choice (1, 2, 4; 1 only for 8x8) and compositor schedule
+ * (1, 0): 90 configurations, each timed with HIP
  * events (best of `repeats`).  It checks that every
  * configuration's images are bit-identical to the first one's, and writes the
  * fastest into *inout_cfg (other fields are kept).  results (host, may be

@@ -318,8 +318,10 @@ fdgs_status check_cfg(const fdgs_render_cfg *cfg, const char *fn) {
     if (!valid_tile(cfg->tile_w, cfg->tile_h))
         return fail(FDGS_ERR_INVALID_ARG, "%s: tile %dx%d not one of 8x8, 16x16, 32x8, 32x16, 32x32", fn, cfg->tile_w,
                     cfg->tile_h);
-    if (cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
-        return fail(FDGS_ERR_INVALID_ARG, "%s: batch %d not one of 64, 128, 256", fn, cfg->batch);
+    if (cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256 &&
+        !((cfg->batch == 512 || cfg->batch == 1024) && cfg->tile_w == 32 && cfg->tile_h == 32))
+        return fail(FDGS_ERR_INVALID_ARG, "%s: batch %d not one of 64, 128, 256 (or 512 with 32x32 tiles)", fn,
+                    cfg->batch);
     if (cfg->pixels_per_thread != 0 && cfg->pixels_per_thread != 1 && cfg->pixels_per_thread != 2 &&
         cfg->pixels_per_thread != 4)
         return fail(FDGS_ERR_INVALID_ARG, "%s: pixels_per_thread %d not one of 0, 1, 2, 4", fn,
@@ -883,9 +885,10 @@ fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_sce
     const int shapes[5][2] = {{16, 16}, {8, 8}, {32, 8}, {32, 16}, {32, 32}};
     for (int sched : {1, 0})
         for (auto &sh : shapes)
-            for (int b : {64, 128, 256})
+            for (int b : {64, 128, 256, 512, 1024})
                 for (int ppt : {1, 2, 4})
-                    if (sh[0] * sh[1] > 64 || ppt == 1) cands.push_back({sh[0], sh[1], b, ppt, sched});
+                    if ((sh[0] * sh[1] > 64 || ppt == 1) && (b <= 256 || sh[0] * sh[1] == 1024))
+                        cands.push_back({sh[0], sh[1], b, ppt, sched});
     hipEvent_t e0 = ctx->get_event(), e1 = ctx->get_event();
     if (!e0 || !e1) return fail(FDGS_ERR_HIP, "%s: event creation failed", fn);
     double best = 1e300;

@@ -120,6 +120,8 @@ __device__ __forceinline__ uint32_t reached_cells(const Rec2D &r, const RenderPa
             if (batch == 64) LAUNCH<32, 32, 64>(ARGS, n_tiles, s);                              \
             else if (batch == 128) LAUNCH<32, 32, 128>(ARGS, n_tiles, s);                       \
             else if (batch == 256) LAUNCH<32, 32, 256>(ARGS, n_tiles, s);                       \
+            else if (batch == 512) LAUNCH<32, 32, 512>(ARGS, n_tiles, s);                       \
+            else if (batch == 1024) LAUNCH<32, 32, 1024>(ARGS, n_tiles, s);                     \
             else ok = false;                                                                    \
         } else {                                                                                \
             ok = false;                                                                         \

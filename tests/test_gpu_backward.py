@@ -43,14 +43,14 @@ def scene_small(n, seed, grow=1.0):
     return sc
 
 
-@pytest.mark.parametrize("n,size,grow,tile", [(64, 32, 1.0, (16, 16)), (2000, 128, 0.5, (16, 16)),
-                                              (2000, 128, 0.5, (32, 16)), (2000, 128, 0.5, (32, 32)),
-                                              (2000, 128, 0.5, (8, 8))])
-def test_backward_matches_oracle_gradient(ctx, n, size, grow, tile):
+@pytest.mark.parametrize("n,size,grow,tile,batch", [(64, 32, 1.0, (16, 16), 128), (2000, 128, 0.5, (16, 16), 128),
+                                                    (2000, 128, 0.5, (32, 16), 128), (2000, 128, 0.5, (32, 32), 128),
+                                                    (2000, 128, 0.5, (32, 32), 1024), (2000, 128, 0.5, (8, 8), 128)])
+def test_backward_matches_oracle_gradient(ctx, n, size, grow, tile, batch):
     from paper_2503_16422_amd.render import GaussianModel
     sc = scene_small(n, seed=3, grow=grow)
     cam = inputs.look_at_camera(0.0, 3.0, size, size)
-    cfg = _lib.default_cfg(bg=(0.1, 0.2, 0.3), tile_w=tile[0], tile_h=tile[1])
+    cfg = _lib.default_cfg(bg=(0.1, 0.2, 0.3), tile_w=tile[0], tile_h=tile[1], batch=batch)
     model = GaussianModel.from_scene(sc, "cuda:0")
     rgb, _, state = ctx.render(model, cam, 0.5, cfg, keep_state=True)
     G = np.random.default_rng(0).standard_normal((3, size, size))

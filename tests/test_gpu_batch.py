@@ -99,9 +99,9 @@ def test_graph_replays_match_eager(ctx, batch_setup):
 def test_autotune_configs_identical(ctx, batch_setup):
     scenes, models, views = batch_setup
     best, results = ctx.autotune(models, views[:5], repeats=2)
-    assert len(results) == 78
+    assert len(results) == 90
     assert all(r["identical"] for r in results)
     assert (best.tile_w, best.tile_h) in [(8, 8), (16, 16), (32, 8), (32, 16), (32, 32)]
-    assert best.batch in (64, 128, 256) and best.pixels_per_thread in (1, 2, 4)
+    assert best.batch in (64, 128, 256, 512, 1024) and best.pixels_per_thread in (1, 2, 4)
     fastest = min(results, key=lambda r: r["ms"])
     assert fastest["ms"] > 0

@@ -277,7 +277,7 @@ def test_tile_and_batch_configs_give_identical_images(ctx):
     model = to_dev(sc)
     base = None
     for tile in ((16, 16), (8, 8), (32, 8), (32, 16), (32, 32)):
-        for batch in (64, 128, 256):
+        for batch in ((64, 128, 256, 512, 1024) if tile == (32, 32) else (64, 128, 256)):
             for cull in (1, 0):
                 for ppt, tcull, sched in ((1, 1, 1), (2, 1, 0), (4, 1, 1), (2, 0, 1), (1, 0, 0)):
                     cfg = _lib.default_cfg(tile_w=tile[0], tile_h=tile[1], batch=batch, temporal_cull=cull,
@@ -382,7 +382,7 @@ def test_full_resolution_masked_frame_sampled(ctx):
     print(f"1352x1014 masked frame: {n}/{sc.n} kept, max err {worst:.2e}, flagged {nflag}")
     # the launch configurations the benchmark's autotuner picks at this size give the same frame
     for tile, batch, ppt, sched in (((32, 32), 256, 2, 1), ((32, 32), 256, 2, 0), ((32, 16), 256, 2, 0),
-                                    ((16, 16), 256, 2, 0)):
+                                    ((16, 16), 256, 2, 0), ((32, 32), 512, 2, 1), ((32, 32), 1024, 2, 0)):
         cfg = _lib.default_cfg(tile_w=tile[0], tile_h=tile[1], batch=batch, pixels_per_thread=ppt, schedule=sched)
         other, _, _ = ctx.render(model, cam, float(frames[f]), cfg, idx=idx, n_idx=count)
         assert torch.equal(other, rgb), (tile, batch, ppt, sched)

@@ -56,7 +56,8 @@ def _saturated_scene():
 
 @pytest.mark.parametrize("tile,ppt,batch", [((16, 16), 2, 256), ((16, 16), 4, 64), ((16, 16), 1, 128),
                                             ((32, 8), 2, 128), ((32, 8), 4, 256), ((8, 8), 1, 64),
-                                            ((32, 16), 2, 256), ((32, 32), 4, 128), ((32, 32), 2, 64)])
+                                            ((32, 16), 2, 256), ((32, 32), 4, 128), ((32, 32), 2, 64),
+                                            ((32, 32), 2, 1024)])
 def test_spatial_score_with_early_stops_and_ragged_edges(ctx, tile, ppt, batch):
     """Pixels that stop early and pixels outside a ragged image leave their
     lanes idle while the rest of the wavefront blends on: every blend weight
