@@ -8,7 +8,8 @@ from oracle import composite as oc
 from oracle import mask as omask
 from oracle import slicing as osl
 from paper_2503_16422_amd import _lib, inputs
-from tests.gpu_helpers import check_culled_binning, compare_image, oracle_settings
+from tests.gpu_helpers import (MAX_FLAGGED_FRAC, cancellation_bound, check_culled_binning, compare_image,
+                               oracle_settings)
 
 pytestmark = pytest.mark.gpu
 
@@ -386,6 +387,59 @@ def test_full_resolution_masked_frame_sampled(ctx):
         cfg = _lib.default_cfg(tile_w=tile[0], tile_h=tile[1], batch=batch, pixels_per_thread=ppt, schedule=sched)
         other, _, _ = ctx.render(model, cam, float(frames[f]), cfg, idx=idx, n_idx=count)
         assert torch.equal(other, rgb), (tile, batch, ppt, sched)
+
+
+def test_single_view_above_bucket_limit_matches_oracle(ctx):
+    """One view of more than 2^20 processed Gaussians takes the radix depth
+    order instead of the depth buckets: lists and ranges bit for bit, and the
+    whole image against the oracle (about 0.9M visible, 2M instances on 30
+    tiles).  Some Gaussians sit 0.2 in front of the camera and cross the
+    image as needles centred thousands of pixels away, where float32 loses
+    digits of the exponent to cancellation: the image tolerance adds the
+    FP64 bound on that loss.  A pixel here walks well over a thousand list
+    entries before it saturates, so the allowed share of flagged pixels
+    scales with the entries walked as the default one does (225 per pixel)."""
+    sc = inputs.tiny_scene(1_100_000, seed=9)
+    sc.log_scale[3] += 3.0
+    assert sc.n > (1 << 20)
+    cam = inputs.look_at_camera(20.0, 3.0, 96, 72)
+    cfg = _lib.default_cfg(tile_w=16, tile_h=16, tile_cull=0)
+    rgb, _, st = ctx.render(to_dev(sc), cam, 0.5, cfg, keep_state=True)
+    b = ctx.binning(st)
+    torch.cuda.synchronize()
+    ost = oracle_settings(cfg)
+    pre = oc.prepare(sc.arrays(), cam, 0.5, ost)
+    assert int(pre.visible.sum()) > 800_000
+    ids, _, ranges = obin.bin_gaussians(pre.rect, pre.depth, pre.visible, 96, 72, 16, 16)
+    assert b["n_inst"] == ids.size
+    assert np.array_equal(b["sorted_ids"].cpu().numpy().astype(np.uint32), ids)
+    assert_same_ranges(b["tile_ranges"].cpu().numpy().astype(np.uint32), ranges)
+    ctx.release(st)
+    ref = oc.composite(pre, cam, ost, mode="rect")
+    bound, walked = cancellation_bound(pre, ids, ranges, 96, 72, 16, 16, ost, walked=True)
+    raw = float(np.abs(rgb.cpu().numpy() - ref.rgb).max())
+    worst, nflag = compare_image(rgb.cpu().numpy(), ref, extra=bound,
+                                 max_flagged=MAX_FLAGGED_FRAC * max(1.0, walked / 225.0))
+    print(f"single view, {sc.n} Gaussians, {ids.size} instances, {walked:.0f} entries walked per pixel: max err {raw:.2e} "
+          f"(bound up to {bound.max():.2e}), beyond bound {worst:.2e}, flagged {nflag}")
+
+
+def test_full_resolution_dense_frame_sampled(ctx):
+    """The unfiltered 3M-Gaussian frame at 1352x1014 in the benchmark's
+    configuration (no temporal or tile culling), on sampled pixels."""
+    sc = inputs.dense_scene(3_000_000, seed=0)
+    cams = inputs.arc_cameras(20, 4.0, 1352, 1014)
+    t = float(inputs.frame_times(300)[123])
+    cfg = _lib.default_cfg(temporal_cull=0, tile_cull=0)
+    model = to_dev(sc)
+    rgb, _, _ = ctx.render(model, cams[5], t, cfg)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    px = rng.integers(0, 1352, 4096)
+    py = rng.integers(0, 1014, 4096)
+    ref = oc.render(sc.arrays(), cams[5], t, oracle_settings(cfg), mode="rect", pixels=(px, py))
+    worst, nflag = compare_image(rgb.cpu().numpy(), ref, pixels=(px, py))
+    print(f"1352x1014 dense frame: max err {worst:.2e}, flagged {nflag}")
 
 
 @pytest.mark.parametrize("dilation", [0.3, 0.0])
