@@ -508,9 +508,10 @@ def test_contributed_mask_matches_oracle_and_keeps_keyframe_images(ctx):
     print(f"contributed mask: {n} of {sc.n} kept; oracle sure {int(sure.sum())}, maybe {int(maybe.sum())}")
 
 
-def test_frames_in_flight_on_two_streams_match_one(ctx):
-    """Two contexts rendering alternate frames on two streams at once (the
-    benchmark's frame loop) give every frame bit for bit as one context does."""
+def test_frames_in_flight_on_four_streams_match_one(ctx):
+    """Four contexts rendering consecutive frames round-robin on four streams
+    at once (the benchmark's frame loop) give every frame bit for bit as one
+    context does."""
     from paper_2503_16422_amd.render import Context
     sc = inputs.tiny_scene(20_000, seed=11)
     model = to_dev(sc)
@@ -518,17 +519,18 @@ def test_frames_in_flight_on_two_streams_match_one(ctx):
     times = [0.1, 0.35, 0.6, 0.85, 0.2, 0.7, 0.45, 0.95]
     cfg = _lib.default_cfg(tile_w=32, tile_h=32, batch=1024, schedule=1, instance_capacity=1 << 22)
     ref = [ctx.render(model, cams[k % 4], t, cfg)[0].clone() for k, t in enumerate(times)]
-    other = Context(0)
-    ctxs = [ctx, other]
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    outs = [torch.empty((len(times), 3, 150, 200), device="cuda") for _ in range(2)]
+    others = [Context(0) for _ in range(3)]
+    ctxs = [ctx] + others
+    streams = [torch.cuda.Stream() for _ in ctxs]
+    outs = torch.empty((len(times), 3, 150, 200), device="cuda")
     torch.cuda.synchronize()
     for k, t in enumerate(times):
-        j = k % 2
+        j = k % len(ctxs)
         with torch.cuda.stream(streams[j]):
-            ctxs[j].render(model, cams[k % 4], t, cfg, out_rgb=outs[j][k])
+            ctxs[j].render(model, cams[k % 4], t, cfg, out_rgb=outs[k])
     torch.cuda.synchronize()
-    other.check_overflow()
-    other.close()
+    for c in others:
+        c.check_overflow()
+        c.close()
     for k in range(len(times)):
-        assert torch.equal(outs[k % 2][k], ref[k]), k
+        assert torch.equal(outs[k], ref[k]), k
