@@ -7,7 +7,7 @@ forward path: keyframe active set (one mask per 10-frame window, built before
 timing) -> slice/project/shade -> visible compaction -> depth sort -> tile
 keys -> tile sort -> ranges -> per-tile blending.  value = frames/s over
 --steps frames, inputs resident in HBM, with consecutive frames dealt
-round-robin over --streams streams (default 4, one context and one image
+round-robin over --streams streams (default 3, one context and one image
 each; the one-stream rate is reported beside it).  Per-stage and roofline
 timings come from a one-stream pass, where kernels do not share the GPU.
 
@@ -362,9 +362,10 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--streams", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=3,
                     help="headline frames dealt round-robin over this many streams (one context each; "
-                         "HIP gives a process 4 hardware queues by default)")
+                         "HIP gives a process 4 hardware queues by default, and the default stream, "
+                         "which builds the masks and runs the one-stream pass, holds one of them)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the masked headline loop (for profiler runs)")
     ap.add_argument("--config", default=None,
