@@ -25,6 +25,14 @@
  * Blend weights (optional, per Gaussian, summed over pixels): alpha_i T_i of
  * every blend, the ray contribution that Eq. 4 sums over all pixels.
  *
+ * Weight slack (optional, per Gaussian, summed over the flagged pixels only):
+ * how far a float32 walk, which may take any of a flagged pixel's
+ * near-threshold decisions the other way, can move the Gaussian's weight at
+ * that pixel: its own weight there (the walk may stop before it or skip it)
+ * plus the largest weight such a walk can give it (its alpha, if it may pass
+ * alpha_min, times the largest transmittance in front of it: the product of
+ * (1 - alpha) over the Gaussians surely above alpha_min, without any stop).
+ *
  * Contributions (optional, per Gaussian, OR-ed over pixels): 1 blended at a
  * pixel whose flags were still 0 after this Gaussian's own decisions (a float32
  * renderer takes the same decisions, so it blends it too); 2 blended at some
@@ -41,6 +49,7 @@ typedef struct {
     const int32_t *rect;                                     /* n x 4 (x0,y0,x1,y1) or NULL */
     int32_t *contrib;                                        /* n, OR-ed contribution bits, or NULL */
     double *weight;                                          /* n, summed alpha T, or NULL */
+    double *weight_slack;                                    /* n, see above, or NULL */
     double bg[3];
     double alpha_min, alpha_max, t_min;
     double rel_alpha, rel_t, rel_depth;
@@ -88,6 +97,37 @@ static void shade_pixel(const oracle_scene *s, const int64_t *list, int64_t nlis
         C1 += s->rgb[3 * i + 1] * w;
         C2 += s->rgb[3 * i + 2] * w;
         T = test;
+    }
+    if (s->weight_slack && flag != 0) {
+        double Tr = 1.0, Th = 1.0;
+        int stopped = 0;
+        for (int64_t k = 0; k < nlist; ++k) {
+            const int64_t i = list[k];
+            if (s->rect) {
+                const int32_t *r = s->rect + 4 * i;
+                if (px < r[0] || px > r[2] || py < r[1] || py > r[3]) continue;
+            }
+            const double dx = sx - s->u[i], dy = sy - s->v[i];
+            const double power = -0.5 * (s->ca[i] * dx * dx + 2.0 * s->cb[i] * dx * dy + s->cc[i] * dy * dy);
+            double alpha = s->opac[i] * exp(power);
+            if (alpha > s->alpha_max) alpha = s->alpha_max;
+            double w_ref = 0.0;   /* this pixel's weight in the walk above */
+            if (!stopped && alpha >= s->alpha_min) {
+                const double test = Tr * (1.0 - alpha);
+                if (test < s->t_min) {
+                    stopped = 1;
+                } else {
+                    w_ref = alpha * Tr;
+                    Tr = test;
+                }
+            }
+            const double w_max = alpha >= s->alpha_min * (1.0 - s->rel_alpha) ? alpha * (1.0 + s->rel_alpha) * Th : 0.0;
+            if (w_ref + w_max > 0.0) {
+                #pragma omp atomic update
+                s->weight_slack[i] += w_ref + w_max;
+            }
+            if (alpha >= s->alpha_min * (1.0 + s->rel_alpha)) Th *= 1.0 - alpha * (1.0 - s->rel_alpha);
+        }
     }
     if (s->contrib && flag != 0) {
         /* a flagged pixel: any Gaussian near or above alpha_min may be blended by a float32 walk */

@@ -163,7 +163,8 @@ def composite_py(pre: Prepared, order, px, py, st: Settings):
 
 class _Scene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in
-                ("u", "v", "ca", "cb", "cc", "opac", "rgb", "depth", "rect", "contrib", "weight")] + [
+                ("u", "v", "ca", "cb", "cc", "opac", "rgb", "depth", "rect", "contrib", "weight",
+                 "weight_slack")] + [
                 ("bg", ctypes.c_double * 3), ("alpha_min", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double),
                 ("rel_alpha", ctypes.c_double), ("rel_t", ctypes.c_double),
@@ -196,6 +197,7 @@ class Image:
     flags: np.ndarray
     contrib: np.ndarray = None   # int32 per processed Gaussian: 1 surely blended, 2 possibly blended
     weight: np.ndarray = None    # float64 per processed Gaussian: summed alpha T over the pixels
+    weight_slack: np.ndarray = None   # float64 per processed Gaussian: weight a float32 walk may move at flagged pixels
 
 
 def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=None,
@@ -209,7 +211,8 @@ def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=No
     pixel does so with every decision so far clear of the thresholds, bit 2
     when a pixel does or, at a flagged pixel, may.  weights: also return, per
     processed Gaussian, the sum over the shaded pixels of its blend weight
-    alpha_i T_i (the summand of Eq. 4).
+    alpha_i T_i (the summand of Eq. 4), and in `weight_slack` the most a
+    float32 walk can move that sum at the flagged pixels (see the C source).
     """
     order = depth_order(pre, use_visible=False)
     keep = np.ones(order.shape, dtype=bool)
@@ -248,6 +251,8 @@ def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=No
     s.contrib = ptr(contrib)
     weight = np.zeros(order.shape[0]) if weights else None
     s.weight = ptr(weight)
+    slack = np.zeros(order.shape[0]) if weights else None
+    s.weight_slack = ptr(slack)
     for k in range(3):
         s.bg[k] = float(st.bg[k])
     s.alpha_min, s.alpha_max, s.t_min = st.alpha_min, st.alpha_max, st.t_min
@@ -262,17 +267,19 @@ def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=No
     inv = np.empty_like(perm)
     inv[perm] = np.arange(npix)
     rgb_o, t_o, f_o = out_rgb[inv].T, out_t[inv], out_f[inv]
-    per_gauss = per_w = None
+    per_gauss = per_w = per_s = None
     if contributions:
         per_gauss = np.zeros(pre.visible.shape[0], dtype=np.int32)
         per_gauss[order] = contrib
     if weights:
         per_w = np.zeros(pre.visible.shape[0])
         per_w[order] = weight
+        per_s = np.zeros(pre.visible.shape[0])
+        per_s[order] = slack
     if full:
         H, W = cam.height, cam.width
-        return Image(rgb_o.reshape(3, H, W), t_o.reshape(H, W), f_o.reshape(H, W), per_gauss, per_w)
-    return Image(rgb_o, t_o, f_o, per_gauss, per_w)
+        return Image(rgb_o.reshape(3, H, W), t_o.reshape(H, W), f_o.reshape(H, W), per_gauss, per_w, per_s)
+    return Image(rgb_o, t_o, f_o, per_gauss, per_w, per_s)
 
 
 def render(scene_arrays, cam, t: float, st: Settings = None, *, idx=None, mode="rect",

@@ -27,14 +27,19 @@ from .composite import Settings, composite, prepare
 from .slicing import covariance_4d, rows, valid_gaussians
 
 
-def spatial_score(scene_arrays, views, st: Settings) -> np.ndarray:
-    """views: sequence of (camera, t).  Returns S^S (float64[n])."""
+def spatial_score(scene_arrays, views, st: Settings, with_slack: bool = False):
+    """views: sequence of (camera, t).  Returns S^S (float64[n]); with_slack=True
+    returns (S^S, slack), slack being the most a float32 renderer's score may
+    differ because of the pixels whose decisions sit near a threshold."""
     n = scene_arrays[0].shape[1]
     score = np.zeros(n)
+    slack = np.zeros(n)
     for cam, t in views:
         pre = prepare(scene_arrays, cam, float(t), st)
-        score += composite(pre, cam, st, mode="rect", weights=True).weight
-    return score
+        img = composite(pre, cam, st, mode="rect", weights=True)
+        score += img.weight
+        slack += img.weight_slack
+    return (score, slack) if with_slack else score
 
 
 def temporal_second_derivative(t, mu_t, sigma44):

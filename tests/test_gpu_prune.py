@@ -31,10 +31,12 @@ def test_spatial_score_matches_oracle_and_telescopes(ctx):
     model = GaussianModel.from_scene(sc, "cuda:0")
     views = [(inputs.look_at_camera(phi, 3.0, 96, 80), t) for phi, t in ((0.0, 0.5), (25.0, 0.45), (-25.0, 0.55))]
     got = ctx.spatial_score(model, views).cpu().numpy().astype(np.float64)
-    ref = oprune.spatial_score(sc.arrays(), views, oracle_settings())
+    ref, slack = oprune.spatial_score(sc.arrays(), views, oracle_settings(), with_slack=True)
     assert got[5] == 0.0
     err = np.abs(got - ref)
-    assert np.all(err <= 2e-4 * ref + 1e-6 * ref.max() + 1e-7), float(err.max())
+    # float32 weights within 2e-4 of the FP64 ones, plus what the pixels whose
+    # decisions sit near a threshold may move (the oracle's slack)
+    assert np.all(err <= 2e-4 * ref + 1e-6 * ref.max() + 1e-7 + slack), float(err.max())
     # per view, the scores add up to the sum over pixels of 1 - T_final
     for cam, t in views:
         one = ctx.spatial_score(model, [(cam, t)]).double()
@@ -77,13 +79,17 @@ def test_spatial_score_with_early_stops_and_ragged_edges(ctx, tile, ppt, batch):
         blended = float((1.0 - T.double()).sum())
         assert abs(float(one.sum()) - blended) <= 1e-5 * blended, (float(one.sum()), blended)
         total = one if total is None else total + one
-    ref = oprune.spatial_score(sc.arrays(), views, oracle_settings())
+    ref, slack = oprune.spatial_score(sc.arrays(), views, oracle_settings(), with_slack=True)
     got = total.cpu().numpy()
-    # float32 stop decisions may differ from the FP64 ones for a few pixels, so
-    # the oracle bounds the sum and nearly every Gaussian, not every one
     assert abs(got.sum() - ref.sum()) <= 1e-4 * ref.sum()
-    close = np.abs(got - ref) <= 2e-4 * ref + 1e-6 * ref.max() + 1e-7
-    assert close.mean() >= 0.999, int((~close).sum())
+    # every Gaussian: float32 weights within 2e-4 of the FP64 ones, plus the
+    # oracle's slack for the pixels whose stop or alpha decisions sit near a
+    # threshold (a float32 walk may take those the other way)
+    err = np.abs(got - ref)
+    bad = err > 2e-4 * ref + 1e-6 * ref.max() + 1e-7 + slack
+    assert not bad.any(), (int(bad.sum()), float(err[bad].max()))
+    print(f"early-stop scores {tile} ppt {ppt} batch {batch}: {int((slack > 0).sum())} Gaussians with slack, "
+          f"max err {float(err.max()):.2e}")
 
 
 def test_variation_score_and_prune_match_oracle(ctx):

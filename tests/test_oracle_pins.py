@@ -553,6 +553,86 @@ def test_spatial_score_sums_to_one_minus_final_transmittance():
     assert np.allclose(both, total, rtol=0, atol=1e-12)
 
 
+def test_spatial_score_of_one_gaussian_is_its_summed_alpha():
+    """Eq. 4 on P-5's scene: in front of a lone Gaussian T = 1, so its score is
+    the sum over the pixels of the analytic alpha (zero below alpha_min)."""
+    s, D, t = 0.05, 3.0, 0.5
+    g = iso_gaussian((0.0, 0.0, 0.0), s, np.array([0.6, -0.2, 1.5]), logit=0.8, t_mean=0.45, log_st=-1.5)
+    st = oc.Settings()
+    score = prune.spatial_score(stack_scenes(g), [(CAM, t)], st)
+    var = (CAM.fx * s / D) ** 2 + st.dilation
+    sigma = 1 / (1 + math.exp(-0.8))
+    p = math.exp(-(t - 0.45) ** 2 / (2 * math.exp(-3.0)))
+    py, px = np.meshgrid(np.arange(64), np.arange(64), indexing="ij")
+    r2 = (px + 0.5 - 32) ** 2 + (py + 0.5 - 32) ** 2
+    alpha = np.minimum(0.99, sigma * p * np.exp(-r2 / (2 * var)))
+    alpha = np.where(alpha < 1 / 255, 0.0, alpha)
+    assert score.shape == (1,)
+    assert abs(score[0] - alpha.sum()) <= 1e-12 * alpha.sum()
+    # two views add
+    two = prune.spatial_score(stack_scenes(g), [(CAM, t), (CAM, t)], st)
+    assert abs(two[0] - 2 * alpha.sum()) <= 1e-12 * alpha.sum()
+
+
+def test_spatial_score_of_two_layers_closed_form_in_either_storage_order():
+    """Eq. 4 on P-6's two overlapping Gaussians: per pixel the near one weighs
+    alpha_1 and the far one alpha_2 (1 - alpha_1), both analytic; the scores
+    follow the Gaussians when their storage order is swapped."""
+    gA = iso_gaussian((0.0, 0.0, 0.3), 0.08, np.array([1.0, 0.0, 0.0]), 1.0)    # nearer (camera at z = 3)
+    gB = iso_gaussian((0.0, 0.0, -0.3), 0.08, np.array([0.0, 1.0, 0.0]), 0.5)
+    st = oc.Settings()
+    py, px = np.meshgrid(np.arange(64), np.arange(64), indexing="ij")
+
+    def alpha_image(pre, i):
+        dx = px + 0.5 - pre.uv[i, 0]
+        dy = py + 0.5 - pre.uv[i, 1]
+        ca, cb, cc = pre.conic[i]
+        al = np.minimum(0.99, pre.opac[i] * np.exp(-0.5 * (ca * dx * dx + 2 * cb * dx * dy + cc * dy * dy)))
+        return np.where(al < 1 / 255, 0.0, al)
+
+    scores = []
+    for scene in (stack_scenes(gA, gB), stack_scenes(gB, gA)):
+        pre = oc.prepare(scene, CAM, 0.5, st)
+        near = int(np.argmin(pre.depth))
+        far = 1 - near
+        a1, a2 = alpha_image(pre, near), alpha_image(pre, far)
+        assert (a1 > 0).sum() > 50 and (a2 > 0).sum() > 50 and (a1 * a2 > 0).sum() > 50
+        expect = np.zeros(2)
+        expect[near] = a1.sum()
+        expect[far] = (a2 * (1 - a1)).sum()
+        got = prune.spatial_score(scene, [(CAM, 0.5)], st)
+        assert np.allclose(got, expect, rtol=1e-12, atol=0), (got, expect)
+        scores.append(got)
+    # gA is stored first in the first scene and second in the other
+    assert np.allclose(scores[0], scores[1][::-1], rtol=1e-12, atol=0)
+    assert scores[0][0] > scores[0][1] * 1.2    # the near Gaussian outweighs the occluded one
+
+
+def test_spatial_score_slack_covers_flipped_threshold_decisions():
+    """The slack bounds how far the score moves when a renderer takes a flagged
+    pixel's near-threshold decisions the other way: moving alpha_min and t_min
+    by less than the flag windows flips exactly such decisions, and every
+    Gaussian's score stays within the slack of the unperturbed one."""
+    sc = inputs.tiny_scene(4000, seed=5)
+    sc.log_scale[:3] += 0.3
+    sc.log_scale[3] += 3.0
+    sc.opacity_logit[:] += 1.0
+    views = [(inputs.look_at_camera(10.0, 3.0, 60, 44), 0.5)]
+    st = oc.Settings()
+    base, slack = prune.spatial_score(sc.arrays(), views, st, with_slack=True)
+    img = oc.render(sc.arrays(), views[0][0], 0.5, st, mode="rect")
+    assert (img.flags != 0).sum() == 0 or slack.max() > 0
+    assert np.all(slack >= 0) and np.all(slack[base == 0] >= 0)
+    flipped = 0
+    for fa, ft in ((1 + 9e-6, 1.0), (1 - 9e-6, 1.0), (1.0, 1 + 9e-5), (1.0, 1 - 9e-5), (1 + 9e-6, 1 - 9e-5)):
+        st2 = oc.Settings(alpha_min=st.alpha_min * fa, t_min=st.t_min * ft)
+        other = prune.spatial_score(sc.arrays(), views, st2)
+        moved = np.abs(other - base)
+        flipped += int((moved > 1e-12).sum())
+        assert np.all(moved <= slack + 1e-12), float((moved - slack).max())
+    assert flipped > 0, "no decision sat near a threshold: the check is empty"
+
+
 def test_temporal_second_derivative_and_variation_bounds():
     """Eq. 5 against central differences of p(t); each Eq. 6 term lies in
     [1, 2]: 2 where p'' vanishes (long-lived, or far from mu_t), near 1 at
