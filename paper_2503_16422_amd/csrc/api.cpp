@@ -751,6 +751,9 @@ fdgs_status enqueue_batch(fdgs_ctx *ctx, const fdgs_model *scenes, const fdgs_vi
     const int64_t img = 3ll * W * H;
     const int32_t n_launch = (n_views + per_launch - 1) / per_launch;
     if (upload && (int32_t)ctx->batch_tables.size() < n_launch) ctx->batch_tables.resize(n_launch);
+    // kernels of an earlier batch on this stream may still read the tables
+    // about to be overwritten (the upload below is ordered on no stream)
+    if (upload) HIP_TRY(hipStreamSynchronize(stream));
     for (int32_t c = 0; c < n_launch; ++c) {
         const int32_t v0 = c * per_launch, V = std::min(per_launch, n_views - v0);
         std::vector<ViewDesc> table(V);
