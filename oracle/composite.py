@@ -201,7 +201,7 @@ class Image:
 
 
 def composite(pre: Prepared, cam, st: Settings, *, mode: str = "rect", pixels=None,
-              rel_alpha: float = 1e-5, rel_t: float = 1e-4, rel_depth: float = 1e-12,
+              rel_alpha: float = 2e-5, rel_t: float = 1e-4, rel_depth: float = 1e-12,
               contributions: bool = False, weights: bool = False) -> Image:
     """Shade the full image (pixels=None) or the given (px, py) arrays.
 

@@ -15,25 +15,49 @@ namespace comp {
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.69314718055994531f;
 
-// Staged form of a record's conic and opacity: base-2 exponent coefficients
-// and log2(opacity), so that
-//   opacity * exp(-1/2 d^T conic d) = exp2(ka dx^2 + kb dx dy + kc dy^2 + lo).
-__device__ __forceinline__ float4 staged_conic(const Rec2D &r) {
-    return make_float4(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y, -0.5f * kLog2e * r.b.z, __log2f(r.b.w));
+// Pixel offsets are taken from the centre of the 32x32 pixel block that holds
+// the tile (the same block for every tile shape, so a pixel's arithmetic does
+// not depend on the tiling): a thread's fx, fy lie in [-15.5, 15.5].
+constexpr int kBlockSize = 32;
+constexpr int kBlockHalf = 16;
+
+// Staged exponent of a record for the block centred at (ox, oy) (absolute
+// pixels).  With the square completed in y (Rec2D::d),
+//   log2(opacity G) = lo + kx dx^2 + ky w^2,   w = dy + s dx = fy + s fx + c0,
+// c0 = -(gy + s gx) taken in float64 from the centre's float pair and the
+// float pair of s: every term of the sum has one sign (kx, ky < 0, lo <= 0),
+// and w, the distance to the footprint's centre line, is formed from
+// block-sized numbers, so the float32 exponent is accurate to a few 1e-6 of
+// its value even for a needle whose centre lies thousands of pixels away.
+struct ExpRec {
+    float gx, gy;   // centre relative to the block centre
+    float s, c0;    // centre line: w = fy + s fx + c0
+    float kx, ky, lo;
+};
+__device__ __forceinline__ ExpRec stage_exp(const Rec2D &r, float ox, float oy) {
+    const double gx = ((double)r.a.x - (double)ox) + (double)r.a.z;
+    const double gy = ((double)r.a.y - (double)oy) + (double)r.a.w;
+    const double s = (double)r.d.z + (double)r.d.w;
+    ExpRec e;
+    e.gx = (float)gx;
+    e.gy = (float)gy;
+    e.s = r.d.z;
+    e.c0 = (float)(-(gy + s * gx));
+    e.kx = r.d.x;
+    e.ky = r.d.y;
+    e.lo = __log2f(r.b.w);
+    return e;
 }
 
-// Base-2 exponent of opacity x 2D Gaussian at offset (dx, dy):
-//   e = ((ka dx) dx + lo) + dy (kb dx + kc dy).
-// The dx-only terms are computed once per column when a thread owns several
-// pixels of one column; every kernel evaluates exactly this expression, so
-// forward, adjoint and all tile shapes take identical alpha decisions.
-__device__ __forceinline__ float exp2_col_a(float4 q, float dx) { return fmaf(q.x * dx, dx, q.w); }
-__device__ __forceinline__ float exp2_col_b(float4 q, float dx) { return q.y * dx; }
-__device__ __forceinline__ float exp2_at(float4 q, float A, float B, float dy) {
-    return fmaf(dy, fmaf(q.z, dy, B), A);
-}
-__device__ __forceinline__ float gauss_exp2(float4 q, float dx, float dy) {
-    return exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), dy);
+// The terms that depend on the thread's column only (computed once for the
+// thread's PPT pixels): A = kx dx^2 + lo and t = s fx + c0; then per pixel
+// e = ky (fy + t)^2 + A.  Every kernel evaluates exactly these expressions,
+// so forward, adjoint and all tile shapes take identical alpha decisions.
+__device__ __forceinline__ float exp2_col_a(float kx, float lo, float dx) { return fmaf(kx * dx, dx, lo); }
+__device__ __forceinline__ float exp2_col_t(float s, float c0, float fx) { return fmaf(s, fx, c0); }
+__device__ __forceinline__ float exp2_at(float ky, float A, float t, float fy) {
+    const float w = fy + t;
+    return fmaf(ky * w, w, A);
 }
 // min(alpha_max, v) for v = exp2(...) >= +0 (or a NaN): non-negative floats
 // order as their bit patterns, so one unsigned minimum gives fminf's result

@@ -2,16 +2,17 @@
 //
 // One workgroup per screen tile; a thread owns 1, 2 or 4 pixels of a column.
 // The tile's depth-ordered list is walked in batches: the workgroup stages a
-// batch of records in LDS (centre relative to the tile origin, pre-scaled
-// conic, opacity, colour), then every pixel evaluates the batch.  A pixel
+// batch of records in LDS (the exponent's staged form relative to the block
+// centre, colour), then every pixel evaluates the batch.  A pixel
 // stops before the Gaussian that would take its transmittance below t_min;
 // the workgroup leaves the list as soon as every pixel has stopped.  No MFMA:
 // per (pixel, Gaussian) pair the work is an exponential and a dozen FMAs, not
 // a contraction.
 //
 // Precision: the centre is stored as a float pair (hi + lo) and re-centred on
-// the tile's 32x32 block while staging, so the per-pair offset dx = px + 0.5 - u
-// is exact to ~1e-6 px even at the right edge of a 1352-px image.
+// the centre of the tile's 32x32 block while staging, and the exponent is
+// evaluated with its square completed (every term of one sign), so alpha is
+// within a few 1e-6 (relative) of its float64 value for any footprint.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -73,10 +74,9 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = (int)threadIdx.x % 64;
     const int lx = (wave % C::CX) * C::CW + lane % C::CW, ly0 = (wave / C::CX) * C::CH + (lane / C::CW) * PPT;
     const int px = tx * TW + lx, py0 = ty * TH + ly0;
-    // Offsets are taken from the origin of the enclosing 32x32 block, which is
-    // the same for every tile shape, so a pixel's arithmetic does not depend on
-    // the tiling.
-    const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;
+    // offsets from the centre of the enclosing 32x32 block (the same for every
+    // tile shape, so a pixel's arithmetic does not depend on the tiling)
+    const int bx0 = ((tx * TW) & ~(kBlockSize - 1)) + kBlockHalf, by0 = ((ty * TH) & ~(kBlockSize - 1)) + kBlockHalf;
     const float fx = (float)(px - bx0) + 0.5f;
     const float ox = (float)bx0, oy = (float)by0;
     const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
@@ -124,12 +124,12 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
             if (k < cnt) {
                 const uint32_t id = a.ids[base + k];
                 const Rec2D r = a.rec[id];
-                const float4 q = staged_conic(r);
+                const ExpRec q = stage_exp(r, ox, oy);
                 if constexpr (kBits) {
                     if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
                 }
-                s_rec[3 * k] = make_float4((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w, q.x, q.y);
-                s_rec[3 * k + 1] = make_float4(q.z, q.w, r.c.x, r.c.y);
+                s_rec[3 * k] = make_float4(q.gx, q.s, q.c0, q.kx);
+                s_rec[3 * k + 1] = make_float4(q.lo, q.ky, r.c.x, r.c.y);
                 s_rec[3 * k + 2] = make_float4(r.c.z, __uint_as_float(id), 0.0f, 0.0f);
             }
             if (kBits && cull) {
@@ -147,11 +147,10 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 for (int k = 0; k < cnt; ++k) {
                     const float4 g = s_rec[3 * k];
                     const float4 h = s_rec[3 * k + 1];
-                    const float4 q = make_float4(g.z, g.w, h.x, h.y);
                     const float dx = fx - g.x;
                     const uint32_t pos = base + k - start + 1;
                     // one pixel: branch, so a wavefront skips the blend when no lane takes it
-                    const float e = exp2_at(q, exp2_col_a(q, dx), exp2_col_b(q, dx), fy[0] - g.y);
+                    const float e = exp2_at(h.y, exp2_col_a(g.w, h.x, dx), exp2_col_t(g.y, g.z, fx), fy[0]);
                     const float alpha = clamp_alpha(__builtin_amdgcn_exp2f(e), amax_bits);
                     if (alpha < amin) continue;
                     const float test = after(T[0], alpha);
@@ -182,17 +181,16 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
             auto blend = [&](int k) {
                 const float4 g = s_rec[3 * k];
                 const float4 h = s_rec[3 * k + 1];
-                const float4 q = make_float4(g.z, g.w, h.x, h.y);
                 const float cb = s_rec[3 * k + 2].x;
                 const float dx = fx - g.x;
-                const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
+                const float A = exp2_col_a(g.w, h.x, dx), B = exp2_col_t(g.y, g.z, fx);
                 const uint32_t pos = base + k - start + 1;
                 bool blended = false;
                 float wsum = 0.0f;
 #pragma unroll
                 for (int p = 0; p < PPT; ++p) {
                     // alpha below alpha_min enters as 0: the test then keeps T (>= t_min), w = 0
-                    const float e = exp2_at(q, A, B, fy[p] - g.y);
+                    const float e = exp2_at(h.y, A, B, fy[p]);
                     const float alpha = clamp_alpha(__builtin_amdgcn_exp2f(e), amax_bits);
                     const float al = alpha >= amin ? alpha : 0.0f;
                     const float test = after(T[p], al);
@@ -290,8 +288,8 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
 template <int TW, int TH, int BATCH, int PPT, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(TW *TH / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 4 ? 1 : 8)))
 composite_kernel(CompArgs a) {
-    // per staged record three float4 at one address: centre (block-relative),
-    // ka, kb | kc, log2 opacity, r, g | b, -, -, -
+    // per staged record three float4 at one address: gx, s, c0, kx |
+    // log2 opacity, ky, r, g | b, id, -, - (the exponent's staged form)
     __shared__ float4 s_rec[3 * BATCH];
     if constexpr (!PERSIST) {
         composite_item<TW, TH, BATCH, PPT, MODE>(a, blockIdx.x, s_rec);

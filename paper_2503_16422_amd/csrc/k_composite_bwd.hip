@@ -46,18 +46,18 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     constexpr int kWords = BATCH / 64;
     __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
     const bool cull = a.rp.tile_cull != 0;
-    __shared__ float2 s_xy[BATCH];
-    __shared__ float4 s_cn[BATCH];    // staged conic and opacity, as in the forward
+    __shared__ float4 s_xy[BATCH];    // centre (block-centred), log2 opacity, 1 / opacity
+    __shared__ float4 s_ex[BATCH];    // s, c0, kx, ky: the exponent as the forward stages it
     __shared__ float4 s_rgb[BATCH];
     __shared__ uint32_t s_id[BATCH];
-    __shared__ float s_io[BATCH];     // 1 / opacity
     __shared__ float s_acc[BATCH * 9]; // per-Gaussian gradient sums of the tile
     const int tile = blockIdx.x;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = lane_id();
     const int lx = (wave % C::CX) * C::CW + lane % C::CW, ly0 = (wave / C::CX) * C::CH + (lane / C::CW) * PPT;
     const int px = tx * TW + lx, py0 = ty * TH + ly0;
-    const int bx0 = (tx * TW) & ~31, by0 = (ty * TH) & ~31;   // as in the forward
+    const int bx0 = ((tx * TW) & ~(kBlockSize - 1)) + kBlockHalf;   // as in the forward
+    const int by0 = ((ty * TH) & ~(kBlockSize - 1)) + kBlockHalf;
     const float fx = (float)(px - bx0) + 0.5f;
     const float ox = (float)bx0, oy = (float)by0;
     const uint32_t start = a.ranges[2 * tile];
@@ -104,11 +104,11 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
             if (k < cnt) {
                 const uint32_t id = a.ids[lo + k];
                 const Rec2D r = a.rec[id];
-                s_xy[k] = make_float2((r.a.x - ox) + r.a.z, (r.a.y - oy) + r.a.w);
-                s_cn[k] = staged_conic(r);
+                const ExpRec q = stage_exp(r, ox, oy);
+                s_xy[k] = make_float4(q.gx, q.gy, q.lo, 1.0f / r.b.w);
+                s_ex[k] = make_float4(q.s, q.c0, q.kx, q.ky);
                 s_rgb[k] = r.c;
                 s_id[k] = id;
-                s_io[k] = 1.0f / r.b.w;
                 if constexpr (kBits) {
                     if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
                 }
@@ -126,18 +126,17 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
         // one record, back to front; every lane of the wavefront takes part
         auto grad_record = [&](int k) {
             const uint32_t pos = lo + k - start;   // position in the tile list
-            const float2 c = s_xy[k];
-            const float4 q = s_cn[k];
+            const float4 c = s_xy[k];
+            const float4 q = s_ex[k];
             const float dx = fx - c.x;
-            const float A = exp2_col_a(q, dx), B = exp2_col_b(q, dx);
+            const float A = exp2_col_a(q.z, c.z, dx), B = exp2_col_t(q.x, q.y, fx);
             float du = 0.f, dv = 0.f, da = 0.f, db = 0.f, dc = 0.f, dop = 0.f;
             float dr = 0.f, dg = 0.f, dbl = 0.f;
             bool hit = false;
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
                 if (pos < last[p]) {
-                    const float dy = fy[p] - c.y;
-                    const float raw = __builtin_amdgcn_exp2f(exp2_at(q, A, B, dy));   // opacity x G
+                    const float raw = __builtin_amdgcn_exp2f(exp2_at(q.w, A, B, fy[p]));   // opacity x G
                     const float alpha = clamp_alpha(raw, amax_bits);
                     if (alpha >= amin) {
                         hit = true;
@@ -156,13 +155,16 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                         S2[p] += col.z * w;
                         if (raw < amax) {
                             // power = -1/2 (a dx^2 + 2 b dx dy + c dy^2); alpha = opacity exp(power)
-                            dop = fmaf(raw * s_io[k], dalpha, dop);       // G = raw / opacity
+                            dop = fmaf(raw * c.w, dalpha, dop);       // G = raw / opacity
                             const float dpow = alpha * dalpha;   // d alpha / d power
+                            const float dy = fy[p] - c.y;
+                            const float wl = fy[p] + B;          // dy + s dx, as in the exponent
                             da = fmaf(-0.5f * dx * dx, dpow, da);
                             db = fmaf(-dx * dy, dpow, db);
                             dc = fmaf(-0.5f * dy * dy, dpow, dc);
-                            du = fmaf(-kLn2 * (2.0f * q.x * dx + q.y * dy), dpow, du);   // (a dx + b dy) dpow
-                            dv = fmaf(-kLn2 * (q.y * dx + 2.0f * q.z * dy), dpow, dv);   // (b dx + c dy) dpow
+                            // d power / d u = -ln 2 d e / d dx with e = kx dx^2 + ky w^2 + lo
+                            du = fmaf(-kLn2 * 2.0f * (q.z * dx + q.w * q.x * wl), dpow, du);   // (a dx + b dy) dpow
+                            dv = fmaf(-kLn2 * 2.0f * (q.w * wl), dpow, dv);                    // (b dx + c dy) dpow
                         }
                     }
                 }

@@ -21,6 +21,7 @@ namespace fdgs {
 namespace {
 
 constexpr int kBlock = kPreprocessBlock;
+constexpr double kLog2eD = 1.4426950408889634;
 
 __global__ void __launch_bounds__(kBlock) slice_kernel(KModel m, double t, const uint32_t *idx,
                                                        int64_t count, float *mean3, float *cov3,
@@ -100,6 +101,13 @@ __device__ __forceinline__ bool preprocess_one(const ViewDesc &vd, int64_t j, co
         rec.a = make_float4(uh, vh, (float)(Pr.u - (double)uh), (float)(Pr.v - (double)vh));
         rec.b = make_float4((float)ca, (float)cb, (float)cc, (float)opac);
         rec.c = make_float4(rgb[0], rgb[1], rgb[2], (float)Pr.z);
+        // square completed in y: every term of the compositor's exponent then
+        // has one sign, so float32 loses nothing to cancellation however
+        // elongated the footprint or far its centre
+        const double sl = -Pr.c01 / Pr.c00;
+        const float s_hi = (float)sl;
+        rec.d = make_float4((float)(-0.5 * kLog2eD / Pr.c00), (float)(-0.5 * kLog2eD * Pr.c00 / det), s_hi,
+                            (float)(sl - (double)s_hi));
         a.out.rec[j] = rec;
         a.out.depth_key[j] = (uint64_t)__double_as_longlong(Pr.z);
         const int4 r4 = make_int4(r.x0, r.y0, r.x1, r.y1);

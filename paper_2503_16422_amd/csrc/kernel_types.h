@@ -25,12 +25,17 @@ struct KModel {
     int64_t n_code;
 };
 
-// Per visible Gaussian record consumed by the compositor (48 B, 16-B aligned).
+// Per visible Gaussian record consumed by the compositor (64 B, 16-B aligned).
 //   a: u_hi, v_hi, u_lo, v_lo    (pixel-space centre as a float pair)
 //   b: conic a, b, c, opacity    (Sigma_2D^{-1} = [[a, b], [b, c]]; sigma * p(t))
 //   c: r, g, b, depth (float32)
+//   d: kx, ky, s_hi, s_lo        (the exponent with the square completed in y,
+//                                 from the float64 Sigma_2D:
+//                                 log2(opacity G) = log2(opacity) + kx dx^2 + ky (dy + s dx)^2,
+//                                 kx = -log2(e) / (2 Sigma_xx), ky = -log2(e) Sigma_xx / (2 det),
+//                                 s = -Sigma_xy / Sigma_xx = s_hi + s_lo)
 struct alignas(16) Rec2D {
-    float4 a, b, c;
+    float4 a, b, c, d;
 };
 
 struct RenderParams {

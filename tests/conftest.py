@@ -17,3 +17,23 @@ def _oracle_built():
     from oracle import build
     if not os.path.exists(build.LIB) or os.path.getmtime(build.LIB) < os.path.getmtime(build.SRC):
         build.build()
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """Flagged-pixel fractions of every image comparison against the oracle
+    (pixels whose decisions sit within the oracle's threshold windows)."""
+    try:
+        from tests.gpu_helpers import IMAGE_RECORDS
+    except Exception:
+        return
+    if not IMAGE_RECORDS:
+        return
+    tr = terminalreporter
+    tr.write_sep("-", "image parity: flagged pixels per comparison")
+    worst = 0.0
+    for test, label, npx, nflag, err, err_flag in IMAGE_RECORDS:
+        frac = nflag / max(npx, 1)
+        worst = max(worst, frac)
+        tr.write_line(f"{frac:9.2e} flagged ({nflag:6d} of {npx:8d}), max err {err:.2e} clean / {err_flag:.2e} "
+                      f"flagged  {test} {label}")
+    tr.write_line(f"largest flagged fraction: {worst:.3e}")

@@ -7,13 +7,14 @@ from oracle import composite as oc
 F32 = lambda x: float(np.float32(x))
 
 # Image tolerance: max |GPU - FP64 oracle| per channel, over pixels the oracle
-# does not flag as sitting within 1e-5 (alpha) / 1e-4 (transmittance) of a
-# threshold decision.
+# does not flag as sitting within 2e-5 (alpha) / 1e-4 (transmittance) of a
+# threshold decision (the alpha window is twice the largest float32 error of
+# the compositors' exponent, tests/test_tolerances.py).
 IMG_TOL = 1e-4
 # A flagged pixel can differ by at most one near-threshold contribution.
 FLAG_TOL = 2e-2
-# Expected flagged fraction: ~(pairs evaluated per pixel) x (2e-5 / ln(255)),
-# e.g. 225 pairs/pixel at 1352x1014 -> ~0.08%.  Allow a few times that.
+# Expected flagged fraction: ~(pairs evaluated per pixel) x (2 x 2e-5 / ln(255)),
+# e.g. 225 pairs/pixel at 1352x1014 -> ~0.16%.
 MAX_FLAGGED_FRAC = 5e-3
 
 
@@ -29,9 +30,14 @@ def oracle_settings(cfg=None, **kw) -> oc.Settings:
     return oc.Settings(**base)
 
 
-def compare_image(gpu_rgb, ref, *, tol=IMG_TOL, pixels=None, extra=None, max_flagged=MAX_FLAGGED_FRAC):
-    """gpu_rgb (3, H, W) numpy; ref an oracle Image (full or sampled).
-    extra: per-pixel allowance added to both tolerances (cancellation_bound);
+# (test, label, pixels compared, flagged pixels, max error over unflagged
+# pixels): every image comparison of the session, printed by the terminal
+# summary hook in conftest.py so that flagged fractions are on record.
+IMAGE_RECORDS = []
+
+
+def compare_image(gpu_rgb, ref, *, tol=IMG_TOL, pixels=None, max_flagged=MAX_FLAGGED_FRAC, label=""):
+    """gpu_rgb (3, H, W) numpy; ref an oracle Image (full or sampled);
     max_flagged: allowed fraction of flagged pixels."""
     if pixels is None:
         g = gpu_rgb.reshape(3, -1)
@@ -43,12 +49,13 @@ def compare_image(gpu_rgb, ref, *, tol=IMG_TOL, pixels=None, extra=None, max_fla
         r = ref.rgb
         f = ref.flags
     err = np.abs(g - r).max(axis=0)
-    if extra is not None:
-        err = np.maximum(err - np.asarray(extra).reshape(-1), 0.0)
     clean = f == 0
     n_flag = int((~clean).sum())
     worst = float(err[clean].max()) if clean.any() else 0.0
     worst_flag = float(err[~clean].max()) if n_flag else 0.0
+    import os
+    IMAGE_RECORDS.append((os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0], label, int(f.size), n_flag,
+                          worst, worst_flag))
     assert worst <= tol, f"max |err| {worst:.3e} over unflagged pixels"
     assert n_flag <= max(2, max_flagged * f.size), f"{n_flag} flagged pixels"
     assert worst_flag <= FLAG_TOL, f"flagged pixel error {worst_flag:.3e}"
@@ -91,63 +98,3 @@ def check_culled_binning(b, pre, st, W, H, tile_w, tile_h):
     missing = np.setdiff1d(need, key_g)
     assert missing.size == 0, f"{missing.size} reached (tile, Gaussian) pairs dropped, first {missing[:4]}"
     return ids_g.size, ids_a.size, need.size
-
-
-def cancellation_bound(pre, ids, ranges, W, H, tile_w, tile_h, st, pixels=None, chunk=512, walked=False):
-    """Per-pixel bound (3-channel max) on how far a float32 compositor may sit
-    from the FP64 image because of cancellation in the exponent.
-
-    The exponent -q/2 with q = a dx^2 + 2 b dx dy + c dy^2 (Eq. 2's Gaussian
-    at the pixel) is summed from terms whose magnitudes add up to
-    Q = |a| dx^2 + 2 |b dx dy| + |c| dy^2.  Far from a needle-shaped
-    Gaussian's centre Q can exceed q by four orders of magnitude, and float32
-    rounding of the terms (and of dx, dy) moves the exponent by up to about
-    4 eps32 Q, so alpha by that relative amount.  The colour's derivative in
-    alpha_i is bounded by 2 T_i max|c| (the Gaussian's own term plus the
-    change of every later transmittance), which gives, to first order,
-        |dC| <= sum_i 2 max|c| T_i alpha_i 4 eps32 Q_i
-    over the blended Gaussians of the pixel, walked in the oracle's FP64 list
-    order with its thresholds.  ids / ranges are the oracle's tile lists.
-    Returns (H, W), or one value per (px, py) pixel when `pixels` is given;
-    with walked=True also the mean number of list entries a pixel evaluates."""
-    eps = float(np.finfo(np.float32).eps)
-    cmax = float(np.abs(pre.rgb).max()) if pre.rgb.size else 0.0
-    if pixels is None:
-        yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
-        px, py = xx.ravel(), yy.ravel()
-    else:
-        px, py = (np.asarray(v, dtype=np.int64) for v in pixels)
-    tile = (py // tile_h) * ((W + tile_w - 1) // tile_w) + px // tile_w
-    out = np.zeros(px.size)
-    n_walked = 0
-    for t in np.unique(tile):
-        sel = np.flatnonzero(tile == t)
-        s, e = int(ranges[t, 0]), int(ranges[t, 1])
-        sx, sy = px[sel] + 0.5, py[sel] + 0.5
-        T = np.ones(sel.size)
-        acc = np.zeros(sel.size)
-        live = np.ones(sel.size, bool)
-        for k0 in range(s, e, chunk):
-            if not live.any():
-                break
-            g = ids[k0:min(k0 + chunk, e)].astype(np.int64)
-            dx = sx[None, :] - pre.uv[g, 0][:, None]
-            dy = sy[None, :] - pre.uv[g, 1][:, None]
-            a, b, c = (pre.conic[g, j][:, None] for j in range(3))
-            q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
-            Q = np.abs(a) * dx * dx + 2.0 * np.abs(b * dx * dy) + np.abs(c) * dy * dy
-            al = np.minimum(st.alpha_max, pre.opac[g][:, None] * np.exp(-0.5 * q))
-            use = al >= st.alpha_min
-            f = np.where(use, 1.0 - al, 1.0)
-            after = T[None, :] * np.cumprod(f, axis=0)          # transmittance after each row
-            before = after / f
-            stop = use & (after < st.t_min)                      # the walk ends at the first such row
-            first = np.where(stop.any(axis=0), stop.argmax(axis=0), g.size)
-            blend = use & (np.arange(g.size)[:, None] < first[None, :]) & live[None, :]
-            acc += (blend * before * al * Q).sum(axis=0)
-            n_walked += int(np.minimum(first + 1, g.size)[live].sum())
-            T = after[-1]
-            live &= first == g.size
-        out[sel] = 8.0 * eps * cmax * acc
-    out = out.reshape(H, W) if pixels is None else out
-    return (out, n_walked / max(px.size, 1)) if walked else out

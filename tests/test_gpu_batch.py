@@ -105,3 +105,63 @@ def test_autotune_configs_identical(ctx, batch_setup):
     assert best.batch in (64, 128, 256, 512, 1024) and best.pixels_per_thread in (1, 2, 4)
     fastest = min(results, key=lambda r: r["ms"])
     assert fastest["ms"] > 0
+
+
+def test_batched_workload_at_full_size(ctx):
+    """A slice of the batched workload at its real shape: two of its scenes
+    (50k and 400k Gaussians), 800x800, keyframe-window masks with the tile
+    test, 256 views rendered in launches of 128 views through a captured HIP
+    graph (replayed with unrelated work in between) and eagerly.  Every view
+    equals its single-view render bit for bit, and three views match the
+    oracle on every pixel."""
+    from paper_2503_16422_amd.render import GaussianModel
+    sizes = inputs.batched_scene_sizes()
+    picks = [0, len(sizes) - 1]
+    scenes = [inputs.long_scene(sizes[s], seed=s) for s in picks]
+    models = [GaussianModel.from_scene(sc, "cuda:0") for sc in scenes]
+    cams = inputs.batch_cameras(800, 800)
+    frames = inputs.frame_times(64)
+    keys = [0, 13, 26, 39, 52, 63]
+    masks = {}
+    for s, m in enumerate(models):
+        for w in range(len(keys) - 1):
+            lo, hi = keys[w], keys[w + 1]
+            _, idx, cnt = ctx.build_active_mask(m, frames[lo:hi + 1], frames[lo], frames[hi],
+                                                _lib.MASK_TEMPORAL_AND_TILE, cams)
+            masks[(s, w)] = (idx, int(cnt.item()))
+    win = lambda f: min(int(np.searchsorted(keys, f, side="right")) - 1, len(keys) - 2)
+    views = []
+    for f in range(0, 64, 2):
+        for c in range(4):
+            for s in range(len(models)):
+                idx, n = masks[(s, win(f))]
+                views.append((s, cams[c], float(frames[f]), idx, n))
+    assert len(views) == 256
+    cfg = _lib.default_cfg(tile_w=32, tile_h=32, batch=512, pixels_per_thread=2, schedule=1)
+    ctx.profile(True)
+    eager = ctx.render_batch(models, views, cfg, views_per_launch=128)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    torch.cuda.synchronize()
+    for k, v in enumerate(views):
+        assert torch.equal(eager[k], single(ctx, models, v, cfg)), k
+    # the largest launch holds at most all instances; the benchmark sizes it the same way
+    cfg.instance_capacity = int(prof["instances"]) + 65536
+    out = torch.zeros_like(eager)
+    for rep in range(3):
+        out.zero_()
+        ctx.render_batch(models, views, cfg, views_per_launch=128, use_graph=True, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        ctx.render(models[0], cams[1], 0.3)
+        torch.cuda.synchronize()
+    ctx.check_overflow()
+    host = eager.cpu().numpy()
+    del out, eager
+    st = oracle_settings()
+    for k in (0, 101, 255):
+        s, cam, t, idx, n = views[k]
+        sel = idx[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+        ref = oc.render(scenes[s].arrays(), cam, t, st, idx=sel, mode="rect")
+        worst, nflag = compare_image(host[k], ref, label=f"batched 800x800 view {k}")
+        print(f"batched view {k} (scene {picks[s]}): max err {worst:.2e}, flagged {nflag}")
