@@ -13,9 +13,13 @@ F32 = lambda x: float(np.float32(x))
 IMG_TOL = 1e-4
 # A flagged pixel can differ by at most one near-threshold contribution.
 FLAG_TOL = 2e-2
-# Expected flagged fraction: ~(pairs evaluated per pixel) x (2 x 2e-5 / ln(255)),
-# e.g. 225 pairs/pixel at 1352x1014 -> ~0.16%.
-MAX_FLAGGED_FRAC = 5e-3
+# Allowed share of flagged pixels.  Flags are the oracle's alone (FP64, seeded
+# inputs), so the shares are fixed numbers; measured at the benchmarked shapes:
+# 2.84e-3 (unfiltered 3M frame, 5984 sampled pixels), 1.87e-3 (masked
+# 1352x1014 frame), 1.88e-3 (batched 800x800 view).  The cap keeps ~40% above
+# the largest; a pixel's chance of a flag grows with the list entries it
+# evaluates (~225 at 1352x1014), so tests whose pixels walk longer lists scale it.
+MAX_FLAGGED_FRAC = 4e-3
 
 
 def oracle_settings(cfg=None, **kw) -> oc.Settings:
