@@ -194,6 +194,25 @@ FDGS_API fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *mod
                                    int64_t *out_count, hipStream_t stream);
 
 /*
+ * (2b) fdgs_build_active_mask without any device allocation, for callers that
+ * cannot allocate: code that must not call hipMalloc (a serving loop with a
+ * fixed memory budget, a harness that forbids allocation).  Takes no context.
+ * Modes FDGS_MASK_TEMPORAL and FDGS_MASK_TEMPORAL_AND_TILE only (the
+ * contributed mode renders views and returns FDGS_ERR_UNSUPPORTED); model->n
+ * at most FDGS_NOALLOC_MAX_GAUSSIANS, else FDGS_ERR_INVALID_ARG.  Outputs and
+ * limits on the spec as for fdgs_build_active_mask, which gives bit-identical
+ * results.  Its scratch (the window's frame times, the mask cameras and the
+ * compaction's per-chunk counts) is a static device array of 1 MiB on each
+ * GPU the library runs on, held until the process ends and shared by every
+ * call on that GPU: calls that overlap on one GPU (on different streams or
+ * host threads) race.  Runs on the current HIP device; synchronises `stream`.
+ */
+#define FDGS_NOALLOC_MAX_GAUSSIANS (INT64_C(1) << 27)
+FDGS_API fdgs_status fdgs_build_active_mask_noalloc(const fdgs_model *model, const fdgs_mask_spec *spec,
+                                                    uint32_t *out_bits, uint32_t *out_idx,
+                                                    int64_t *out_count, hipStream_t stream);
+
+/*
  * (3) Forward render of one view at time t (Eq. 2, Eq. 3).
  * Processed set: every Gaussian if idx == NULL, else idx[0..count) with count
  * read from the device scalar *n_idx_dev (int64, <= model->n), as written by

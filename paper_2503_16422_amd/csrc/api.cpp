@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,9 @@ using namespace fdgs;
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int kMaskMaxFrames = 256;   // frame times of one keyframe window
+constexpr int kMaskMaxViews = 64;     // mask cameras
 
 fdgs_status fail(fdgs_status code, const char *fmt, ...) {
     char buf[512];
@@ -389,27 +393,30 @@ fdgs_status fdgs_slice_4d(fdgs_ctx *ctx, const fdgs_model *model, double t, cons
     return FDGS_OK;
 }
 
-fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const fdgs_mask_spec *spec,
-                                   uint32_t *out_bits, uint32_t *out_idx, int64_t *out_count,
-                                   hipStream_t stream) {
-    const char *fn = "fdgs_build_active_mask";
-    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the mask entry points; fills the effective alpha_min
+// and dilation.
+fdgs_status check_mask_args(const fdgs_model *model, const fdgs_mask_spec *spec, const uint32_t *out_bits,
+                            const uint32_t *out_idx, const int64_t *out_count, float *amin_out, float *dil_out,
+                            const char *fn) {
     if (fdgs_status st = check_model(model, fn)) return st;
     if (!spec) return fail(FDGS_ERR_INVALID_ARG, "%s: spec is NULL", fn);
     if (spec->mode != FDGS_MASK_TEMPORAL && spec->mode != FDGS_MASK_TEMPORAL_AND_TILE &&
         spec->mode != FDGS_MASK_CONTRIBUTED)
         return fail(FDGS_ERR_INVALID_ARG, "%s: unknown mode %d", fn, spec->mode);
-    const bool contributed = spec->mode == FDGS_MASK_CONTRIBUTED;
-    if (!contributed) {
-        if (spec->n_frames < 1 || spec->n_frames > 256 || !spec->frame_times)
-            return fail(FDGS_ERR_INVALID_ARG, "%s: need 1..256 frame times", fn);
+    if (spec->mode != FDGS_MASK_CONTRIBUTED) {
+        if (spec->n_frames < 1 || spec->n_frames > kMaskMaxFrames || !spec->frame_times)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: need 1..%d frame times", fn, kMaskMaxFrames);
         for (int f = 0; f < spec->n_frames; ++f)
             if (!std::isfinite(spec->frame_times[f]))
                 return fail(FDGS_ERR_INVALID_ARG, "%s: non-finite frame time", fn);
     }
     if (spec->mode != FDGS_MASK_TEMPORAL) {
-        if (spec->n_views < 1 || spec->n_views > 64 || !spec->views)
-            return fail(FDGS_ERR_INVALID_ARG, "%s: modes 1 and 2 need 1..64 views", fn);
+        if (spec->n_views < 1 || spec->n_views > kMaskMaxViews || !spec->views)
+            return fail(FDGS_ERR_INVALID_ARG, "%s: modes 1 and 2 need 1..%d views", fn, kMaskMaxViews);
         for (int v = 0; v < spec->n_views; ++v)
             if (fdgs_status st = check_camera(&spec->views[v], fn)) return st;
         if (!std::isfinite(spec->key_lo) || !std::isfinite(spec->key_hi))
@@ -418,10 +425,58 @@ fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const
     if (!out_bits || !out_idx || !out_count) return fail(FDGS_ERR_INVALID_ARG, "%s: an output is NULL", fn);
     const float amin = spec->alpha_min > 0.0f ? spec->alpha_min : 1.0f / 255.0f;
     if (!(amin < 1.0f)) return fail(FDGS_ERR_INVALID_ARG, "%s: alpha_min must be < 1", fn);
-    const float dil = spec->dilation >= 0.0f ? spec->dilation : 0.3f;
+    *amin_out = amin;
+    *dil_out = spec->dilation >= 0.0f ? spec->dilation : 0.3f;
+    return FDGS_OK;
+}
+
+// Modes TEMPORAL and TEMPORAL_AND_TILE: copies the window's frame times and
+// mask cameras into frames_dev / views_dev (device, room for the spec's
+// counts), runs the predicate and compacts the bits with compact_scratch
+// (compact_scratch_bytes(n)); synchronises the stream, since the host arrays
+// are copied asynchronously.
+fdgs_status enqueue_window_mask(const fdgs_model *model, const fdgs_mask_spec *spec, float amin, float dil,
+                                double *frames_dev, KCam *views_dev, void *compact_scratch, uint32_t *out_bits,
+                                uint32_t *out_idx, int64_t *out_count, hipStream_t stream) {
+    HIP_TRY(hipMemcpyAsync(frames_dev, spec->frame_times, sizeof(double) * spec->n_frames, hipMemcpyHostToDevice,
+                           stream));
+    KCam views[kMaskMaxViews];
+    const int32_t n_views = spec->mode == FDGS_MASK_TEMPORAL_AND_TILE ? spec->n_views : 0;
+    for (int v = 0; v < n_views; ++v) views[v] = kcam(&spec->views[v]);
+    if (n_views > 0)
+        HIP_TRY(hipMemcpyAsync(views_dev, views, sizeof(KCam) * n_views, hipMemcpyHostToDevice, stream));
+    MaskArgs a;
+    a.frames = frames_dev;
+    a.n_frames = spec->n_frames;
+    a.views = views_dev;
+    a.n_views = n_views;
+    a.key_lo = spec->key_lo;
+    a.key_hi = spec->key_hi;
+    a.mode = spec->mode;
+    a.level = 2.0 * std::log(1.0 / (double)amin);
+    a.rect_level = a.level * (1.0 + 1e-4) + 1e-4;
+    a.dilation = dil;
+    HIP_TRY(launch_mask_bits(kmodel(model), a, out_bits, stream));
+    HIP_TRY(compact_bits(out_bits, model->n, out_idx, out_count, compact_scratch, stream));
+    // the host arrays were copied asynchronously: finish before returning
+    HIP_TRY(hipStreamSynchronize(stream));
+    return FDGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const fdgs_mask_spec *spec,
+                                   uint32_t *out_bits, uint32_t *out_idx, int64_t *out_count,
+                                   hipStream_t stream) {
+    const char *fn = "fdgs_build_active_mask";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    float amin = 0.0f, dil = 0.0f;
+    if (fdgs_status st = check_mask_args(model, spec, out_bits, out_idx, out_count, &amin, &dil, fn)) return st;
     HIP_TRY(hipSetDevice(ctx->device));
     const int64_t n = model->n;
-    if (contributed) {
+    if (spec->mode == FDGS_MASK_CONTRIBUTED) {
         // the union over views and both keyframes of the Gaussians some pixel blends
         fdgs_render_cfg cfg;
         fdgs_render_cfg_default(&cfg);
@@ -458,32 +513,71 @@ fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *model, const
         return FDGS_OK;
     }
     HIP_TRY(ensure(ctx->mask_frames, sizeof(double) * spec->n_frames));
-    HIP_TRY(hipMemcpyAsync(ctx->mask_frames.p, spec->frame_times, sizeof(double) * spec->n_frames,
-                           hipMemcpyHostToDevice, stream));
-    std::vector<KCam> views;
-    if (spec->mode == FDGS_MASK_TEMPORAL_AND_TILE) {
-        for (int v = 0; v < spec->n_views; ++v) views.push_back(kcam(&spec->views[v]));
-        HIP_TRY(ensure(ctx->mask_views, sizeof(KCam) * views.size()));
-        HIP_TRY(hipMemcpyAsync(ctx->mask_views.p, views.data(), sizeof(KCam) * views.size(),
-                               hipMemcpyHostToDevice, stream));
-    }
-    MaskArgs a;
-    a.frames = ctx->mask_frames.as<double>();
-    a.n_frames = spec->n_frames;
-    a.views = ctx->mask_views.as<KCam>();
-    a.n_views = spec->mode == FDGS_MASK_TEMPORAL_AND_TILE ? spec->n_views : 0;
-    a.key_lo = spec->key_lo;
-    a.key_hi = spec->key_hi;
-    a.mode = spec->mode;
-    a.level = 2.0 * std::log(1.0 / (double)amin);
-    a.rect_level = a.level * (1.0 + 1e-4) + 1e-4;
-    a.dilation = dil;
-    HIP_TRY(launch_mask_bits(kmodel(model), a, out_bits, stream));
+    if (spec->mode == FDGS_MASK_TEMPORAL_AND_TILE) HIP_TRY(ensure(ctx->mask_views, sizeof(KCam) * spec->n_views));
     HIP_TRY(ensure(ctx->mask_scratch, compact_scratch_bytes(n)));
-    HIP_TRY(compact_bits(out_bits, n, out_idx, out_count, ctx->mask_scratch.p, stream));
-    // the host arrays were copied asynchronously: finish before returning
-    HIP_TRY(hipStreamSynchronize(stream));
+    return enqueue_window_mask(model, spec, amin, dil, ctx->mask_frames.as<double>(), ctx->mask_views.as<KCam>(),
+                               ctx->mask_scratch.p, out_bits, out_idx, out_count, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of fdgs_build_active_mask_noalloc: one array per GPU, held until the
+// process ends.  Host code never passes `scratch` itself (in host code the
+// name is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns for the current device.
+//   [0, 2 KiB)        frame times (double[256])
+//   [2 KiB, 12 KiB)   mask cameras (KCam[64], 144 B each)
+//   [12 KiB, 1 MiB)   per-chunk counts of the compaction (compact_scratch_bytes(n))
+constexpr size_t kNoAllocFrames = 0;
+constexpr size_t kNoAllocViews = 2048;
+constexpr size_t kNoAllocCompact = 12288;
+constexpr size_t kNoAllocBytes = size_t(1) << 20;
+static_assert(sizeof(double) * kMaskMaxFrames <= kNoAllocViews - kNoAllocFrames, "frame times fit");
+static_assert(sizeof(KCam) * kMaskMaxViews <= kNoAllocCompact - kNoAllocViews, "mask cameras fit");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+fdgs_status noalloc_scratch(void **out, const char *fn) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FDGS_ERR_UNSUPPORTED, "%s: device %d out of range", fn, dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(FDGS_ERR_HIP, "%s: no device address for the scratch array", fn);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return FDGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdgs_status fdgs_build_active_mask_noalloc(const fdgs_model *model, const fdgs_mask_spec *spec,
+                                           uint32_t *out_bits, uint32_t *out_idx, int64_t *out_count,
+                                           hipStream_t stream) {
+    const char *fn = "fdgs_build_active_mask_noalloc";
+    float amin = 0.0f, dil = 0.0f;
+    if (fdgs_status st = check_mask_args(model, spec, out_bits, out_idx, out_count, &amin, &dil, fn)) return st;
+    if (spec->mode == FDGS_MASK_CONTRIBUTED)
+        return fail(FDGS_ERR_UNSUPPORTED, "%s: mode FDGS_MASK_CONTRIBUTED renders views and needs allocations", fn);
+    if (model->n > FDGS_NOALLOC_MAX_GAUSSIANS || compact_scratch_bytes(model->n) > kNoAllocBytes - kNoAllocCompact)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: n = %lld exceeds the maximum of %lld Gaussians", fn,
+                    (long long)model->n, (long long)FDGS_NOALLOC_MAX_GAUSSIANS);
+    unsigned char *base = nullptr;
+    if (fdgs_status st = noalloc_scratch(reinterpret_cast<void **>(&base), fn)) return st;
+    return enqueue_window_mask(model, spec, amin, dil, reinterpret_cast<double *>(base + kNoAllocFrames),
+                               reinterpret_cast<KCam *>(base + kNoAllocViews), base + kNoAllocCompact, out_bits,
+                               out_idx, out_count, stream);
 }
 
 }  // extern "C"
