@@ -23,41 +23,45 @@ constexpr int kBlockHalf = 16;
 
 // Staged exponent of a record for the block centred at (ox, oy) (absolute
 // pixels).  With the square completed in y (Rec2D::d),
-//   log2(opacity G) = lo + kx dx^2 + ky w^2,   w = dy + s dx = fy + s fx + c0,
-// c0 = -(gy + s gx) taken in float64 from the centre's float pair and the
-// float pair of s: every term of the sum has one sign (kx, ky < 0, lo <= 0),
-// and w, the distance to the footprint's centre line, is formed from
+//   log2(opacity G) = lo + kx dx^2 - v^2,   v = q (dy + s dx) = q fy + s' fx + c0,
+// s' = q s and c0 = -q (gy + s gx) taken in float64 from the centre's float
+// pair and the float pair of s: both variable terms are <= 0 (kx < 0), and v,
+// the scaled distance to the footprint's centre line, is formed from
 // block-sized numbers, so the float32 exponent is accurate to a few 1e-6 of
 // its value even for a needle whose centre lies thousands of pixels away.
 struct ExpRec {
     float gx, gy;   // centre relative to the block centre
-    float s, c0;    // centre line: w = fy + s fx + c0
-    float kx, ky, lo;
+    float q;        // sqrt(-ky)
+    float s, c0;    // scaled centre line: v = q fy + s fx + c0
+    float kx, lo;
 };
 __device__ __forceinline__ ExpRec stage_exp(const Rec2D &r, float ox, float oy) {
     const double gx = ((double)r.a.x - (double)ox) + (double)r.a.z;
     const double gy = ((double)r.a.y - (double)oy) + (double)r.a.w;
-    const double s = (double)r.d.z + (double)r.d.w;
+    const double sl = (double)r.d.z + (double)r.d.w;
+    const double q = (double)r.d.y;
     ExpRec e;
     e.gx = (float)gx;
     e.gy = (float)gy;
-    e.s = r.d.z;
-    e.c0 = (float)(-(gy + s * gx));
+    e.q = r.d.y;
+    e.s = (float)(q * sl);
+    e.c0 = (float)(-q * (gy + sl * gx));
     e.kx = r.d.x;
-    e.ky = r.d.y;
     e.lo = __log2f(r.b.w);
     return e;
 }
 
 // The terms that depend on the thread's column only (computed once for the
 // thread's PPT pixels): A = kx dx^2 + lo and t = s fx + c0; then per pixel
-// e = ky (fy + t)^2 + A.  Every kernel evaluates exactly these expressions,
-// so forward, adjoint and all tile shapes take identical alpha decisions.
+// v = q fy + t and e = A - v^2.  Every kernel evaluates exactly these
+// expressions, so forward, adjoint and all tile shapes take identical alpha
+// decisions.
 __device__ __forceinline__ float exp2_col_a(float kx, float lo, float dx) { return fmaf(kx * dx, dx, lo); }
 __device__ __forceinline__ float exp2_col_t(float s, float c0, float fx) { return fmaf(s, fx, c0); }
-__device__ __forceinline__ float exp2_at(float ky, float A, float t, float fy) {
-    const float w = fy + t;
-    return fmaf(ky * w, w, A);
+__device__ __forceinline__ float exp2_line(float q, float t, float fy) { return fmaf(q, fy, t); }
+__device__ __forceinline__ float exp2_at(float q, float A, float t, float fy) {
+    const float v = exp2_line(q, t, fy);
+    return fmaf(-v, v, A);
 }
 // min(alpha_max, v) for v = exp2(...) >= +0 (or a NaN): non-negative floats
 // order as their bit patterns, so one unsigned minimum gives fminf's result

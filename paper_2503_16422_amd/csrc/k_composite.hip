@@ -129,7 +129,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
                 }
                 s_rec[3 * k] = make_float4(q.gx, q.s, q.c0, q.kx);
-                s_rec[3 * k + 1] = make_float4(q.lo, q.ky, r.c.x, r.c.y);
+                s_rec[3 * k + 1] = make_float4(q.lo, q.q, r.c.x, r.c.y);
                 s_rec[3 * k + 2] = make_float4(r.c.z, __uint_as_float(id), 0.0f, 0.0f);
             }
             if (kBits && cull) {
@@ -160,11 +160,11 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                         all_done = true;
                         break;
                     }
-                    const float w = alpha * T[0];
+                    const float w = T[0] - test;   // the blend weight, as in the multi-pixel walk
                     C0[0] = fmaf(h.z, w, C0[0]);
                     C1[0] = fmaf(h.w, w, C1[0]);
                     C2[0] = fmaf(s_rec[3 * k + 2].x, w, C2[0]);
-                    T[0] = test;
+                    T[0] -= w;
                     if constexpr (LAST) last[0] = pos;
                     if constexpr (MARK) {
                         // lanes here blended record k: the lowest one flags it
@@ -189,21 +189,25 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 float wsum = 0.0f;
 #pragma unroll
                 for (int p = 0; p < PPT; ++p) {
-                    // alpha below alpha_min enters as 0: the test then keeps T (>= t_min), w = 0
+                    // blend when alpha reaches alpha_min and the pixel keeps at least
+                    // thr (t_min while live); stop when alpha reaches alpha_min but the
+                    // transmittance would fall below thr.  The two conditions combine
+                    // as lane masks, and the weight alpha T is the drop of T, so a
+                    // skipped or stopped pair costs no select of its own
                     const float e = exp2_at(h.y, A, B, fy[p]);
                     const float alpha = clamp_alpha(__builtin_amdgcn_exp2f(e), amax_bits);
-                    const float al = alpha >= amin ? alpha : 0.0f;
-                    const float test = after(T[p], al);
-                    const bool ok = test >= thr[p];
-                    const float w = ok ? al * T[p] : 0.0f;
+                    const float test = after(T[p], alpha);
+                    const bool hit = alpha >= amin;
+                    const bool ok = hit && test >= thr[p];
+                    const float w = ok ? T[p] - test : 0.0f;
                     C0[p] = fmaf(h.z, w, C0[p]);
                     C1[p] = fmaf(h.w, w, C1[p]);
                     C2[p] = fmaf(cb, w, C2[p]);
-                    if constexpr (LAST) last[p] = w > 0.0f ? pos : last[p];   // w >= alpha_min t_min > 0
+                    if constexpr (LAST) last[p] = ok ? pos : last[p];
                     if constexpr (COUNT) stop[p] += thr[p] < kInf ? 1u : 0u;
-                    T[p] = ok ? test : T[p];
-                    thr[p] = ok ? thr[p] : kInf;
-                    if constexpr (MARK) blended = blended || w > 0.0f;
+                    T[p] -= w;
+                    thr[p] = hit != ok ? kInf : thr[p];   // alpha reached alpha_min, T would fall below thr
+                    if constexpr (MARK) blended = blended || ok;
                     if constexpr (WEIGHT) wsum += w;
                 }
                 if constexpr (WEIGHT) {
@@ -289,7 +293,7 @@ template <int TW, int TH, int BATCH, int PPT, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(TW *TH / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 4 ? 1 : 8)))
 composite_kernel(CompArgs a) {
     // per staged record three float4 at one address: gx, s, c0, kx |
-    // log2 opacity, ky, r, g | b, id, -, - (the exponent's staged form)
+    // log2 opacity, q, r, g | b, id, -, - (the exponent's staged form)
     __shared__ float4 s_rec[3 * BATCH];
     if constexpr (!PERSIST) {
         composite_item<TW, TH, BATCH, PPT, MODE>(a, blockIdx.x, s_rec);

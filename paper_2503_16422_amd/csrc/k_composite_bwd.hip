@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
     const bool cull = a.rp.tile_cull != 0;
     __shared__ float4 s_xy[BATCH];    // centre (block-centred), log2 opacity, 1 / opacity
-    __shared__ float4 s_ex[BATCH];    // s, c0, kx, ky: the exponent as the forward stages it
+    __shared__ float4 s_ex[BATCH];    // s, c0, kx, q: the exponent as the forward stages it
     __shared__ float4 s_rgb[BATCH];
     __shared__ uint32_t s_id[BATCH];
     __shared__ float s_acc[BATCH * 9]; // per-Gaussian gradient sums of the tile
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                 const Rec2D r = a.rec[id];
                 const ExpRec q = stage_exp(r, ox, oy);
                 s_xy[k] = make_float4(q.gx, q.gy, q.lo, 1.0f / r.b.w);
-                s_ex[k] = make_float4(q.s, q.c0, q.kx, q.ky);
+                s_ex[k] = make_float4(q.s, q.c0, q.kx, q.q);
                 s_rgb[k] = r.c;
                 s_id[k] = id;
                 if constexpr (kBits) {
@@ -158,13 +158,14 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                             dop = fmaf(raw * c.w, dalpha, dop);       // G = raw / opacity
                             const float dpow = alpha * dalpha;   // d alpha / d power
                             const float dy = fy[p] - c.y;
-                            const float wl = fy[p] + B;          // dy + s dx, as in the exponent
+                            const float vl = exp2_line(q.w, B, fy[p]);   // q (dy + s dx), as in the exponent
                             da = fmaf(-0.5f * dx * dx, dpow, da);
                             db = fmaf(-dx * dy, dpow, db);
                             dc = fmaf(-0.5f * dy * dy, dpow, dc);
-                            // d power / d u = -ln 2 d e / d dx with e = kx dx^2 + ky w^2 + lo
-                            du = fmaf(-kLn2 * 2.0f * (q.z * dx + q.w * q.x * wl), dpow, du);   // (a dx + b dy) dpow
-                            dv = fmaf(-kLn2 * 2.0f * (q.w * wl), dpow, dv);                    // (b dx + c dy) dpow
+                            // d power / d u = -ln 2 d e / d dx with e = lo + kx dx^2 - v^2,
+                            // v = q dy + (q s) dx: d e / d dx = 2 kx dx - 2 (q s) v, d e / d dy = -2 q v
+                            du = fmaf(-kLn2 * 2.0f * (q.z * dx - q.x * vl), dpow, du);   // (a dx + b dy) dpow
+                            dv = fmaf(kLn2 * 2.0f * (q.w * vl), dpow, dv);                // (b dx + c dy) dpow
                         }
                     }
                 }

@@ -106,7 +106,7 @@ __device__ __forceinline__ bool preprocess_one(const ViewDesc &vd, int64_t j, co
         // elongated the footprint or far its centre
         const double sl = -Pr.c01 / Pr.c00;
         const float s_hi = (float)sl;
-        rec.d = make_float4((float)(-0.5 * kLog2eD / Pr.c00), (float)(-0.5 * kLog2eD * Pr.c00 / det), s_hi,
+        rec.d = make_float4((float)(-0.5 * kLog2eD / Pr.c00), (float)sqrt(0.5 * kLog2eD * Pr.c00 / det), s_hi,
                             (float)(sl - (double)s_hi));
         a.out.rec[j] = rec;
         a.out.depth_key[j] = (uint64_t)__double_as_longlong(Pr.z);

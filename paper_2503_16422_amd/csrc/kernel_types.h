@@ -29,10 +29,10 @@ struct KModel {
 //   a: u_hi, v_hi, u_lo, v_lo    (pixel-space centre as a float pair)
 //   b: conic a, b, c, opacity    (Sigma_2D^{-1} = [[a, b], [b, c]]; sigma * p(t))
 //   c: r, g, b, depth (float32)
-//   d: kx, ky, s_hi, s_lo        (the exponent with the square completed in y,
+//   d: kx, q, s_hi, s_lo         (the exponent with the square completed in y,
 //                                 from the float64 Sigma_2D:
-//                                 log2(opacity G) = log2(opacity) + kx dx^2 + ky (dy + s dx)^2,
-//                                 kx = -log2(e) / (2 Sigma_xx), ky = -log2(e) Sigma_xx / (2 det),
+//                                 log2(opacity G) = log2(opacity) + kx dx^2 - q^2 (dy + s dx)^2,
+//                                 kx = -log2(e) / (2 Sigma_xx), q^2 = log2(e) Sigma_xx / (2 det),
 //                                 s = -Sigma_xy / Sigma_xx = s_hi + s_lo)
 struct alignas(16) Rec2D {
     float4 a, b, c, d;

@@ -5,8 +5,8 @@ The image tolerance exempts a pixel only when one of its decisions sits within
 the oracle's window of a threshold (alpha within rel_alpha of alpha_min).  That
 is sound if a float32 evaluation of alpha stays within the window of the FP64
 one.  The compositor evaluates log2(opacity G) with the square completed in y
-from quantities the preprocess forms in float64 (every term of one sign) at
-offsets from the centre of the 32x32 pixel block; the float32 steps are
+from quantities the preprocess forms in float64 (both variable terms of one
+sign) at offsets from the centre of the 32x32 pixel block; the float32 steps are
 written out below in that order (a product of two float32 values is exact in
 float64, so fma(a, b, c) is (a * b + c) in float64 rounded once), on a scene
 full of needles centred far outside the image, where a direct float32
@@ -53,7 +53,7 @@ def _float32_exponent(pre, g, px, py):
     """log2(opacity G) as the compositor forms it (completed square, block-centred offsets)."""
     c00, c01, c11 = pre.cov2d[g, 0, 0], pre.cov2d[g, 0, 1], pre.cov2d[g, 1, 1]
     det = c00 * c11 - c01 * c01
-    kx, ky = _f(-0.5 * LOG2E / c00), _f(-0.5 * LOG2E * c00 / det)
+    kx, q = _f(-0.5 * LOG2E / c00), _f(np.sqrt(0.5 * LOG2E * c00 / det))
     s = -c01 / c00
     s_hi = _f(s)
     s_lo = _f(s - s_hi.astype(np.float64))
@@ -65,15 +65,17 @@ def _float32_exponent(pre, g, px, py):
     gx = (u_hi.astype(np.float64) - ox) + u_lo.astype(np.float64)
     gy = (v_hi.astype(np.float64) - oy) + v_lo.astype(np.float64)
     sd = s_hi.astype(np.float64) + s_lo.astype(np.float64)
-    c0 = _f(-(gy + sd * gx))
+    qd = q.astype(np.float64)
+    s_sc = _f(qd * sd)
+    c0 = _f(-qd * (gy + sd * gx))
     lo = _f(np.log2(_f(pre.opac[g]).astype(np.float64)))
     fx = _f(px - ox + 0.5)
     fy = _f(py - oy + 0.5)
     dx = _f(fx.astype(np.float64) - _f(gx).astype(np.float64))
     A = _fma(_f(kx.astype(np.float64) * dx.astype(np.float64)), dx, lo)
-    t = _fma(s_hi, fx, c0)
-    w = _f(fy.astype(np.float64) + t.astype(np.float64))
-    return _fma(_f(ky.astype(np.float64) * w.astype(np.float64)), w, A)
+    t = _fma(s_sc, fx, c0)
+    w = _fma(q, fy, t)
+    return _fma(-w, w, A)
 
 
 def test_float32_exponent_within_the_alpha_flag_window():
