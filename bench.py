@@ -48,11 +48,23 @@ def sync():
     torch.cuda.synchronize()
 
 
-def stage_bytes(name, prof, frames, masked, pixels):
+# instances per tile above which the range kernel binary-searches each tile's
+# two bounds instead of scanning key boundaries (the library's threshold)
+RANGES_SEARCH_ABOVE = 2048
+# fp32 operations of the adjoint compositor per (pixel, Gaussian) pair it
+# differentiates (exponent, alpha, transmittance recovery, colour and alpha
+# adjoints, the five geometry terms)
+BWD_FLOPS_PER_PAIR = 40
+# LDS bytes a wavefront reads per staged record it walks: two 16-byte and one
+# 4-byte broadcast read per lane
+LDS_BYTES_PER_RECORD_WAVE = 64 * 36
+
+
+def stage_bytes(name, prof, frames, masked, pixels, n_tiles=None):
     """Algorithmic HBM bytes a stage must move over the profiled frames."""
     P, V, M = prof["processed"], prof["visible"], prof["instances"]
     if name == "preprocess":
-        return P * (68 + (4 if masked else 0) + 4) + V * (192 + 48)
+        return P * (68 + (4 if masked else 0) + 4) + V * (192 + 64)
     if name == "compact":
         return P * (1 + 4) + V * 8
     if name == "depth_sort":
@@ -64,7 +76,11 @@ def stage_bytes(name, prof, frames, masked, pixels):
     if name == "tile_sort":
         return M * 16 * 2
     if name == "ranges":
-        return M * 4
+        if n_tiles and M / frames > RANGES_SEARCH_ABOVE * n_tiles:
+            # two binary searches per tile (one 4-byte key per probe), two bounds written
+            probes = 2 * math.ceil(math.log2(max(M / frames, 2)))
+            return frames * n_tiles * (probes * 4 + 8)
+        return M * 4 + frames * (n_tiles or 0) * 8
     if name == "composite":
         return M * 40 + frames * pixels * 12
     return 0
@@ -182,7 +198,7 @@ def timed_fps_pipelined(ctxs, outs, model, cams, frames, masks, frame_window, cf
     return steps / dt, dt
 
 
-def profile_stages(ctx, model, cams, frames, masks, frame_window, cfg, steps, start, out, masked, pixels):
+def profile_stages(ctx, model, cams, frames, masks, frame_window, cfg, steps, start, out, masked, pixels, n_tiles):
     """Per-stage HIP-event times of `steps` frames (the kernels the timed loop
     runs) and the algorithmic HBM rate of each stage."""
     from paper_2503_16422_amd import _lib
@@ -196,13 +212,62 @@ def profile_stages(ctx, model, cams, frames, masks, frame_window, cfg, steps, st
         if not calls:
             continue
         avg_ms = prof["ms"][name] / calls
-        nbytes = stage_bytes(name, prof, steps, masked, pixels)
+        nbytes = stage_bytes(name, prof, steps, masked, pixels, n_tiles)
         entry = {"avg_ms": round(avg_ms, 5), "algorithmic_GBps": round(nbytes / calls / (avg_ms * 1e-3) / 1e9, 1)}
         entry["hbm_frac"] = round(entry["algorithmic_GBps"] / HBM_PEAK_GBS, 4)
         stages[name] = entry
     per_frame = {"processed": prof["processed"] / steps, "visible": prof["visible"] / steps,
                  "instances": prof["instances"] / steps}
     return stages, per_frame
+
+
+def frame_time_percentiles(ctx, model, cams, frames, masks, frame_window, cfg, steps, start, out):
+    """p50 / p99 of per-frame GPU time (HIP events around each frame's
+    launches, one stream) over `steps` frames of the loop."""
+    import numpy as np
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        run_frames(ctx, model, cams, frames, masks, frame_window, cfg, 1, start + k, out)
+        ev[k][1].record()
+    sync()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"p50_ms": round(float(np.percentile(ms, 50)), 4), "p99_ms": round(float(np.percentile(ms, 99)), 4),
+            "mean_ms": round(float(ms.mean()), 4), "frames": steps}
+
+
+def hbm_copy_peak():
+    """Device-to-device copy of a 1 GiB buffer: bytes read + written per second."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    sync()
+    gbps = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
+
+
+def tiles_of(cfg, W, H):
+    return ((W + cfg.tile_w - 1) // cfg.tile_w) * ((H + cfg.tile_h - 1) // cfg.tile_h)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def cpu_baseline(scene, jobs):
@@ -221,7 +286,66 @@ def cpu_baseline(scene, jobs):
             "sample": f"{len(jobs)} whole masked 1352x1014 frames of the headline workload "
                       f"(~{int(np.mean([j[0].size for j in jobs]))} Gaussians each): FP64 slice, projection and SH "
                       f"in NumPy, then rect-mode per-pixel blending in C/OpenMP; {dt:.1f} s wall",
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": cpu_model()}
+
+
+def keyframe_visibility(ctx, model, cams, frames, frame_window, cfg, kept_mode1, out, steps, warmup):
+    """The paper's own keyframe masks (Sec. 4.2.2: Gaussians some pixel of some
+    view blends at the window's keyframes) and the redundancy measures of
+    Sec. 4.1: active ratio |A_t| / N and activation IoU of A_0 and A_t, with
+    A_t the Gaussians blended at time t in any of the cameras."""
+    import numpy as np
+    from paper_2503_16422_amd import _lib
+    n = model.n
+    a0 = ctx.build_active_mask(model, [], float(frames[0]), float(frames[0]), _lib.MASK_CONTRIBUTED, cams)[0]
+    ratio, iou = {}, {}
+    for f in range(0, len(frames), 20):
+        t = float(frames[f])
+        at = ctx.build_active_mask(model, [], t, t, _lib.MASK_CONTRIBUTED, cams)[0]
+        ca, cb, cab = (int(x) for x in ctx.mask_overlap(a0, at, n).cpu())
+        ratio[f] = round(cb / n, 4)
+        iou[f] = round(cab / max(ca + cb - cab, 1), 4)
+    masks2, _, _, ms2, kept2 = build_masks(ctx, model, cams, mode=_lib.MASK_CONTRIBUTED)
+    worst = max_instances(ctx, model, cams, frames, masks2, frame_window, cfg, steps + warmup, 0)
+    cfg2 = _lib.default_cfg(**{k: getattr(cfg, k) for k in ("tile_w", "tile_h", "batch", "pixels_per_thread",
+                                                            "schedule")})
+    cfg2.instance_capacity = int(worst * 1.05) + 4096
+    fps2, _ = timed_fps(ctx, model, cams, frames, masks2, frame_window, cfg2, steps, warmup, out)
+    return {"active_ratio_by_frame": ratio, "activation_iou_vs_frame0": iou,
+            "contributed_mask_build_ms_per_window": round(ms2, 3),
+            "contributed_kept_per_window_mean": int(np.mean(kept2)),
+            "kept_vs_tile_mask": round(float(np.mean(kept2)) / float(np.mean(kept_mode1)), 4),
+            "masked_fps_contributed_masks_one_stream": round(fps2, 1)}
+
+
+def finetune_timing(ctx, scene, cams, frames, masks, frame_window, cfg, steps=40):
+    """Masked fine-tuning (Sec. 4.2.2) on the headline scene: one 1352x1014 view
+    per step, the frame's window mask, every parameter tensor updated by Adam;
+    targets rendered from a second scene.  ms per step, host-synchronised
+    (the loop reads each step's loss)."""
+    from paper_2503_16422_amd import inputs
+    from paper_2503_16422_amd.finetune import MaskedFineTuner
+    from paper_2503_16422_amd.render import GaussianModel
+    model = GaussianModel.from_scene(scene, "cuda:0")
+    other = GaussianModel.from_scene(inputs.long_scene(scene.n, seed=1), "cuda:0")
+    views, mask_at = [], {}
+    for k in range(20):
+        c, f = frame_schedule(k * 7, len(cams), len(frames))
+        t = float(frames[f])
+        mask_at[t] = masks[frame_window[f]]
+        idx, cnt = mask_at[t]
+        views.append((cams[c], t, ctx.render(other, cams[c], t, cfg, idx=idx, n_idx=cnt)[0].clone()))
+    del other
+    tuner = MaskedFineTuner(ctx, model, views, mask_of=lambda t: mask_at[t], cfg=cfg)
+    for k in range(5):
+        tuner.step(k)
+    sync()
+    t0 = time.perf_counter()
+    losses = [tuner.step(k) for k in range(steps)]
+    sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_iter": round(ms, 3), "steps": steps, "views": len(views),
+            "loss_first_last": [round(losses[0], 1), round(losses[-1], 1)]}
 
 
 # tile shapes and LDS batches tried for the fwd+bwd loop (the forward autotuner
@@ -278,14 +402,21 @@ def fwd_bwd(ctx, steps, warmup):
     tw, th = (int(x) for x in best.split("/")[0].split("x"))
     cfg = _lib.default_cfg(tile_w=tw, tile_h=th, batch=int(best.split("/b")[1]))
     ms = timed(cfg, steps, warmup)
-    ctx.profile(True)
+    ctx.profile(True, count_pairs=True)
     for _ in range(3):
         step(cfg)
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
     stage_ms = {k: round(v / 3, 4) for k, v in prof["ms"].items() if v > 0}
     release()
-    return ms, views, stage_ms, {"chosen": best, "sweep_ms_per_iter": sweep}
+    # the adjoint walks the pairs the forward evaluated, back to front
+    pairs = prof["pairs"] / 3
+    bwd_ms = prof["ms"]["bwd_composite"] / 3
+    adj = {"pairs_per_iter": int(pairs), "ms_per_iter": round(bwd_ms, 4),
+           "flops_per_pair": BWD_FLOPS_PER_PAIR,
+           "achieved_TFLOPs": round(pairs * BWD_FLOPS_PER_PAIR / (bwd_ms * 1e-3) / 1e12, 3)}
+    adj["frac_of_fp32_peak"] = round(adj["achieved_TFLOPs"] / FP32_PEAK_TFLOPS, 4)
+    return ms, views, stage_ms, {"chosen": best, "sweep_ms_per_iter": sweep}, adj
 
 
 def batched(ctx, steps=3):
@@ -393,6 +524,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = Context(0)
+    # measured rates of this device: HBM by a 1 GiB copy, LDS and VALU by micro-benchmarks
+    peaks = ctx.measure_peaks()
+    peaks["hbm_copy_GBps"] = round(hbm_copy_peak(), 1)
+    log(f"[bench] measured peaks: {json.dumps(peaks)}")
     if args.copy_calibration:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -401,7 +536,7 @@ def main():
         sync()
         del a, b
     if args.fwd_bwd_only:
-        ms_iter, views, fb_stages, fb_tiles = fwd_bwd(ctx, args.steps, args.warmup)
+        ms_iter, views, fb_stages, fb_tiles, _ = fwd_bwd(ctx, args.steps, args.warmup)
         log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter; tiles {fb_tiles}; stages {json.dumps(fb_stages)}")
         return
     W, H = 1352, 1014
@@ -486,15 +621,29 @@ def main():
         if not calls:
             continue
         avg_ms = prof["ms"][name] / calls
-        nbytes = stage_bytes(name, prof, K, True, W * H)
+        nbytes = stage_bytes(name, prof, K, True, W * H, tiles_of(cfg, W, H))
         entry = {"avg_ms": round(avg_ms, 5), "algorithmic_GBps": round(nbytes / calls / (avg_ms * 1e-3) / 1e9, 1)}
         entry["hbm_frac"] = round(entry["algorithmic_GBps"] / HBM_PEAK_GBS, 4)
+        entry["hbm_frac_of_copy"] = round(entry["algorithmic_GBps"] / peaks["hbm_copy_GBps"], 4)
         stages[name] = entry
     comp = stages["composite"]
     pairs_per_frame = prof["pairs"] / K
     comp_tflops = pairs_per_frame * FLOPS_PER_PAIR / (comp["avg_ms"] * 1e-3) / 1e12
     comp["pairs_per_frame"] = int(pairs_per_frame)
     comp["achieved_TFLOPs"] = round(comp_tflops, 3)
+    comp["valu_frac_of_measured"] = round(pairs_per_frame * FLOPS_PER_PAIR / 2 / (comp["avg_ms"] * 1e-3)
+                                          / peaks["valu_fma_lane_ops_per_s"], 4)
+    # LDS: every (record, wavefront) the walk visits reads the staged record;
+    # a wavefront evaluates 64 x pixels-per-thread pairs per record it walks
+    lds_bps = pairs_per_frame / (64 * cfg.pixels_per_thread) * LDS_BYTES_PER_RECORD_WAVE / (comp["avg_ms"] * 1e-3)
+    comp["lds_TBps"] = round(lds_bps / 1e12, 2)
+    comp["lds_frac_of_measured"] = round(lds_bps / peaks["lds_broadcast_Bps"], 4)
+    # the paper's two rates: "FPS" times the whole render call (host work
+    # included: fps1), "Raster FPS" the rasterisation alone (GPU time of a
+    # frame's launches, events around each frame)
+    frame_pct = frame_time_percentiles(ctx, model, cams, frames, masks, frame_window, cfg, K, Wu, out)
+    raster_ms = frame_pct["mean_ms"]
+    log(f"[bench] frame time {frame_pct}")
     dominant = max(stages, key=lambda s: stages[s]["avg_ms"])
     if dominant == "composite":
         kname = (f"composite_kernel<{cfg.tile_w}, {cfg.tile_h}, {cfg.batch}, {cfg.pixels_per_thread}, 0, "
@@ -530,6 +679,16 @@ def main():
         log(f"[bench] grid: {grid}")
         extra["masked_scene_grid_fps"] = grid
 
+        # ---- the paper's keyframe visibility masks, active ratio and IoU ---------------
+        extra["keyframe_visibility"] = keyframe_visibility(ctx, model, cams, frames, frame_window, cfg, kept, out,
+                                                           K, Wu)
+        log(f"[bench] keyframe visibility: {json.dumps(extra['keyframe_visibility'])}")
+
+        # ---- masked fine-tuning step time ------------------------------------------
+        ft_cfg = _lib.default_cfg(instance_capacity=0)
+        extra["masked_finetune"] = finetune_timing(ctx, scene, cams, frames, masks, frame_window, ft_cfg)
+        log(f"[bench] masked fine-tuning: {json.dumps(extra['masked_finetune'])}")
+
         # ---- SH vector quantisation (post-processing): codebook build, then the same frames --
         k_vq, it_vq = 4096, 10
         ctx.sh_kmeans(model, k_vq, 1)                                  # warm-up (allocations)
@@ -557,7 +716,8 @@ def main():
         vanilla = _lib.default_cfg(temporal_cull=0, tile_cull=0)
         d_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, vanilla, n_dense, 3, out, start=2000)
         d_stages, d_work = profile_stages(ctx, dmodel, cams, frames, None, frame_window, vanilla, n_dense, 2003,
-                                          out, False, W * H)
+                                          out, False, W * H, tiles_of(vanilla, W, H))
+        d_pct = frame_time_percentiles(ctx, dmodel, cams, frames, None, frame_window, vanilla, n_dense, 2003, out)
         log(f"[bench] dense vanilla stages: {json.dumps(d_stages)}")
         dt_fps, _ = timed_fps(ctx, dmodel, cams, frames, None, frame_window, _lib.default_cfg(temporal_cull=0),
                               n_dense, 3, out, start=2000)
@@ -568,12 +728,14 @@ def main():
         log(f"[bench] dense: vanilla {d_fps:.1f}, +tile cull {dt_fps:.1f}, +temporal cull {dc_fps:.1f}, "
             f"+mask {dm_fps:.1f} frames/s")
         extra["dense_3M"] = {"vanilla_fps": round(d_fps, 2), "vanilla_stages": d_stages,
+                             "vanilla_frame_time": d_pct,
                              "vanilla_per_frame": {k: int(v) for k, v in d_work.items()},
                              "vanilla_tile_cull_fps": round(dt_fps, 2),
                              "temporal_cull_fps": round(dc_fps, 2),
                              "masked_fps": round(dm_fps, 2), "mask_build_ms_per_window": round(dmask_ms, 2),
                              "kept_mean": int(np.mean(dkept))}
-        extra["masked_200k_vs_dense_3M_vanilla"] = round(fps / d_fps, 2)
+        # like for like: both rates from one stream, one frame after another
+        extra["masked_200k_vs_dense_3M_vanilla_one_stream"] = round(fps1 / d_fps, 2)
         del dmodel, dmasks
         torch.cuda.empty_cache()
 
@@ -585,9 +747,10 @@ def main():
 
         # ---- forward + backward ------------------------------------------------------
         log("[bench] fwd+bwd: 500k Gaussians, 4 views")
-        ms_iter, views, fb_stages, fb_tiles = fwd_bwd(ctx, 20, 5)
+        ms_iter, views, fb_stages, fb_tiles, adj = fwd_bwd(ctx, 20, 5)
         extra["fwd_bwd_ms_per_iter"] = round(ms_iter, 3)
         extra["fwd_bwd_stage_ms_per_iter"] = fb_stages
+        extra["fwd_bwd_adjoint_compositor"] = adj
         extra["fwd_bwd_config"] = {"gaussians": 500_000, "views": views, "resolution": [W, H],
                                    "loss": "0.5*sum((I-I*)^2), targets rendered from a second seed",
                                    "tiles": fb_tiles}
@@ -620,8 +783,10 @@ def main():
                        round(r["ms"] / len(tune_views), 4) for r in sweep},
                    "gaussians": 200_000, "resolution": [W, H], "mask_windows": len(masks),
                    "kept_per_window_mean": int(np.mean(kept)), "per_frame": per_frame,
-                   "mask_build_ms_per_window": round(mask_ms, 3)},
+                   "mask_build_ms_per_window": round(mask_ms, 3),
+                   "raster_fps_one_stream": round(1e3 / raster_ms, 1), "frame_time_one_stream": frame_pct},
         "roofline": roof,
+        "peaks_measured": peaks,
         "stages": stages,
         "cpu_baseline": cpu,
     }

@@ -194,6 +194,21 @@ FDGS_API fdgs_status fdgs_build_active_mask(fdgs_ctx *ctx, const fdgs_model *mod
                                    int64_t *out_count, hipStream_t stream);
 
 /*
+ * Overlap of two active sets, for the redundancy measures of Sec. 4.1:
+ * out[0] = |a|, out[1] = |b|, out[2] = |a and b|, counted over the first n
+ * bits of the bit arrays a and b (device, ceil(n/32) uint32 words each, bit
+ * i%32 of word i/32, as fdgs_build_active_mask writes them; bits past n are
+ * ignored); out is a device int64[3], written on `stream`.  With A_t the set
+ * of Gaussians that some pixel of some view blends at time t
+ * (fdgs_build_active_mask, mode FDGS_MASK_CONTRIBUTED, key_lo = key_hi = t):
+ * the active ratio at t is |A_t| / n and the activation IoU between frames 0
+ * and t is |A_0 and A_t| / (|A_0| + |A_t| - |A_0 and A_t|).  Runs on the
+ * current HIP device; 0 <= n < 2^31.
+ */
+FDGS_API fdgs_status fdgs_mask_overlap(const uint32_t *bits_a, const uint32_t *bits_b, int64_t n,
+                                       int64_t *out, hipStream_t stream);
+
+/*
  * (2b) fdgs_build_active_mask without any device allocation, for callers that
  * cannot allocate: code that must not call hipMalloc (a serving loop with a
  * fixed memory budget, a harness that forbids allocation).  Takes no context.
@@ -234,8 +249,11 @@ FDGS_API fdgs_status fdgs_render_forward(fdgs_ctx *ctx, const fdgs_model *model,
                                 fdgs_state **keep_state, hipStream_t stream);
 
 /*
- * (4) Adjoint of the forward pass recorded in `state`.  dL_drgb (device,
- * [3][H][W]) is the gradient of a scalar loss with respect to out_rgb.
+ * (4) Adjoint of the forward pass recorded in `state`: Eq. 2 and Eq. 3
+ * differentiated back to front through the blend (transmittance recovered from
+ * the final T, no per-pixel lists), then through the projection, Eq. 1's
+ * slicing and the activations to the model's parameters (Sec. 3).  dL_drgb
+ * (device, [3][H][W]) is the gradient of a scalar loss with respect to out_rgb.
  * Gradients are ACCUMULATED (+=) into the caller's device buffers, laid out
  * like fdgs_model: mean[4][n], log_scale[4][n], q_left[4][n], q_right[4][n],
  * opacity_logit[n], sh[16][3][n].  Gaussians that were not processed or not
@@ -437,6 +455,18 @@ typedef struct {
     int64_t instances;
     uint64_t pairs;                  /* (pixel, Gaussian) evaluations      */
 } fdgs_profile;
+
+/*
+ * Rates of the device, measured with micro-benchmarks (a few milliseconds;
+ * synchronises `stream`), against which kernel rates are reported:
+ *   out[0] LDS bytes/s delivered to lanes when every lane of a wavefront
+ *          reads the same 16 bytes (the compositors' staged-record reads),
+ *   out[1] LDS bytes/s with lane-distinct 16-byte reads,
+ *   out[2] float32 FMA lane-operations/s of the vector ALUs (non-packed),
+ *   out[3] compute units.
+ * out is host double[4].
+ */
+FDGS_API fdgs_status fdgs_measure_peaks(fdgs_ctx *ctx, double *out, hipStream_t stream);
 
 /* Profiling for subsequent calls on this context: 0 off; 1 stage events and
  * work counts (the compositor is the one that runs unprofiled); 2 as 1 plus

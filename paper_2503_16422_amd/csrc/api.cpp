@@ -159,6 +159,7 @@ struct fdgs_ctx {
     hipStream_t capture_stream = nullptr;   // graphs are captured here (the caller's may be the null stream)
     std::vector<unsigned char> graph_key;
     Buf tune_ref, tune_img, tune_diff;
+    Buf probe_sink;                // fdgs_measure_peaks
 
     hipEvent_t get_event() {
         if (!free_events.empty()) {
@@ -264,6 +265,7 @@ fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
     release(ctx->mask_scratch);
     release(ctx->mask_flags);
     release(ctx->mask_img);
+    release(ctx->probe_sink);
     for (Buf *b : {&ctx->prune_a, &ctx->prune_b, &ctx->prune_c, &ctx->prune_d, &ctx->prune_e, &ctx->prune_times,
                    &ctx->vq_scratch})
         release(*b);
@@ -562,6 +564,27 @@ fdgs_status noalloc_scratch(void **out, const char *fn) {
 
 extern "C" {
 
+fdgs_status fdgs_measure_peaks(fdgs_ctx *ctx, double *out, hipStream_t stream) {
+    const char *fn = "fdgs_measure_peaks";
+    if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
+    if (!out) return fail(FDGS_ERR_INVALID_ARG, "%s: out is NULL", fn);
+    HIP_TRY(hipSetDevice(ctx->device));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    HIP_TRY(ensure(ctx->probe_sink, sizeof(float) * 8 * (size_t)std::max(cus, 1)));
+    HIP_TRY(measure_peaks(ctx->probe_sink.as<float>(), out, stream));
+    return FDGS_OK;
+}
+
+fdgs_status fdgs_mask_overlap(const uint32_t *bits_a, const uint32_t *bits_b, int64_t n, int64_t *out,
+                              hipStream_t stream) {
+    const char *fn = "fdgs_mask_overlap";
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(FDGS_ERR_INVALID_ARG, "%s: n out of range", fn);
+    if (!out || (n > 0 && (!bits_a || !bits_b))) return fail(FDGS_ERR_INVALID_ARG, "%s: a pointer is NULL", fn);
+    HIP_TRY(launch_mask_overlap(bits_a, bits_b, n, out, stream));
+    return FDGS_OK;
+}
+
 fdgs_status fdgs_build_active_mask_noalloc(const fdgs_model *model, const fdgs_mask_spec *spec,
                                            uint32_t *out_bits, uint32_t *out_idx, int64_t *out_count,
                                            hipStream_t stream) {
@@ -584,6 +607,23 @@ fdgs_status fdgs_build_active_mask_noalloc(const fdgs_model *model, const fdgs_m
 
 namespace {
 
+// Cell marks in the tile keys for the compositor layout of this
+// configuration: cells of cell_w x cell_h pixels, one per wavefront (16
+// pixels wide where the tile allows, 64 x pixels-per-thread pixels); only
+// with tile culling, several pixels per thread, several cells per tile, and
+// (view, tile) numbers that leave the top 8 key bits free.
+void set_cell_marks(RenderParams *rp, int32_t ppt, int64_t n_keys) {
+    const int tw = rp->tile_w, th = rp->tile_h;
+    if (tw * th == 64) ppt = 1;   // 8x8 tiles: one pixel per thread
+    const int cw = (tw >= 16 && th >= 4 * ppt) ? 16 : tw;
+    const int ch = 64 * ppt / cw;
+    const int nw = (tw / cw) * (th / ch);
+    if (rp->tile_cull && ppt > 1 && nw > 1 && nw <= 8 && th / ch <= 4 && n_keys <= (int64_t)kTileKeyMask + 1) {
+        rp->cell_w = cw;
+        rp->cell_h = ch;
+    }
+}
+
 RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
     RenderParams rp;
     rp.tile_w = cfg->tile_w;
@@ -598,6 +638,7 @@ RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
     rp.temporal_cull = cfg->temporal_cull ? 1 : 0;
     rp.tile_cull = cfg->tile_cull ? 1 : 0;
     rp.vanilla_level = 2.0 * std::log(1.0 / (double)cfg->alpha_min) * (1.0 + 1e-4) + 1e-4;
+    rp.cell_w = rp.cell_h = 0;
     return rp;
 }
 
@@ -611,10 +652,12 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
                         float *out_rgb, float *out_T, bool need_state, hipStream_t stream, uint8_t *contrib,
                         float *weight) {
     const char *fn = "fdgs_render";
-    const RenderParams rp = make_params(cfg, W, H);
+    RenderParams rp = make_params(cfg, W, H);
     const int64_t tiles_per_view = (int64_t)rp.tiles_x * rp.tiles_y;
     const int64_t n_keys = tiles_per_view * V;
     if (n_keys >= (int64_t(1) << 31)) return fail(FDGS_ERR_INVALID_ARG, "%s: too many tiles x views", fn);
+    const int32_t ppt = cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt;
+    set_cell_marks(&rp, ppt, n_keys);
     const int64_t n_max = n_total;
     const int64_t npx = (int64_t)W * H;
 
@@ -734,7 +777,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     {
         StageTimer tm(ctx, FDGS_STAGE_RANGES, stream);
         HIP_TRY(launch_tile_ranges(S->sorted_keys, counts + 1, capacity, (int32_t)n_keys, S->ranges.as<uint32_t>(),
-                                   stream));
+                                   stream, rp.cell_w > 0 ? kTileKeyMask : 0xffffffffu));
     }
     float *T_out = need_state ? S->T_final.as<float>() : out_T;
     uint64_t *acc = nullptr;
@@ -746,9 +789,9 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     {
         StageTimer tm(ctx, FDGS_STAGE_COMPOSITE, stream);
         HIP_TRY(launch_composite(rp, W, H, V, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
-                                 S->rect.as<int32_t>(), out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
+                                 S->sorted_keys, out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
                                  acc && ctx->prof == 2 ? acc + 3 : nullptr,
-                                 cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt,
+                                 ppt,
                                  cfg->schedule ? S->sched.as<uint32_t>() : nullptr, contrib, weight, stream));
     }
     if (need_state && out_T)
@@ -1064,6 +1107,7 @@ fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *
         StageTimer tm(ctx, FDGS_STAGE_BWD_COMPOSITE, stream);
         HIP_TRY(launch_fill_u32(S->g2d.as<uint32_t>(), 9 * std::max<int64_t>(S->n_max, 1), 0u, stream));
         HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ranges.as<uint32_t>(), S->sorted_ids,
+                                          S->sorted_keys,
                                           S->rec.as<Rec2D>(), S->T_final.as<float>(), S->n_contrib.as<uint32_t>(),
                                           dL_drgb, S->g2d.as<float>(), S->n_max, stream));
     }

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build", "fdgs")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FDGS_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "k_preprocess.hip", "k_scan.hip", "k_sort.hip", "k_bucket.hip", "k_composite.hip", "k_composite_bwd.hip", "k_backward.hip", "k_prune.hip", "k_optim.hip", "k_vq.hip"]
+SOURCES = ["api.cpp", "k_preprocess.hip", "k_scan.hip", "k_sort.hip", "k_bucket.hip", "k_composite.hip", "k_composite_bwd.hip", "k_backward.hip", "k_prune.hip", "k_optim.hip", "k_vq.hip", "k_probe.hip"]
 HEADERS = ["fdgs_internal.h", "kernel_types.h", "dev_util.h", "dev_gauss.h", "dev_cull.h", "dev_composite.h", os.path.join("..", "..", "include", "fdgs.h")]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",

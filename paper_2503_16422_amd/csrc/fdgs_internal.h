@@ -116,7 +116,7 @@ hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, cons
 hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, const int64_t *n_dev,
                              int64_t n_max, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
-                              int32_t n_tiles, uint32_t *ranges, hipStream_t s);
+                              int32_t n_tiles, uint32_t *ranges, hipStream_t s, uint32_t key_mask = 0xffffffffu);
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 // *out = number of 32-bit words where a and b differ.
@@ -136,16 +136,24 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 // blends; weight (optional): weight[id] += the entry's summed blend weights
 // alpha T (state and counters are not recorded in either case).
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
-                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const int32_t *rect,
+                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const uint32_t *keys,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
                             uint64_t *pair_counter, int32_t pixels_per_thread, uint32_t *sched,
                             uint8_t *contrib, float *weight, hipStream_t s);
 // bits[w] bit j = (flags[32 w + j] != 0), j < 32, for n flags.
 hipError_t launch_flags_to_bits(const uint8_t *flags, int64_t n, uint32_t *bits, hipStream_t s);
+// Rates measured on the current device (sink: device float[8 x CUs], never
+// written in practice): out[0] LDS bytes/s read as broadcasts, out[1] LDS
+// bytes/s read at lane-distinct addresses, out[2] float32 FMA lane-operations/s,
+// out[3] compute units.  Synchronises s.
+hipError_t measure_peaks(float *sink, double *out, hipStream_t s);
+// out[0..2] = popcounts of a, b and a & b over the first n bits (device int64[3]).
+hipError_t launch_mask_overlap(const uint32_t *a, const uint32_t *b, int64_t n, int64_t *out, hipStream_t s);
 
 // Backward.
 hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
-                                     const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
+                                     const uint32_t *ranges, const uint32_t *ids, const uint32_t *keys,
+                                     const Rec2D *rec,
                                      const float *T_final, const uint32_t *n_contrib,
                                      const float *dL_drgb, float *g2d, int64_t n_proc_max,
                                      hipStream_t s);

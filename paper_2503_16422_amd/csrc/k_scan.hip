@@ -267,6 +267,35 @@ __global__ void __launch_bounds__(kNT) bits_compact_kernel(const uint32_t *bits,
     }
 }
 
+// Population counts of two active-set bit arrays and of their intersection
+// (one workgroup; a few hundred thousand words at most, so one pass of
+// coalesced loads and a block reduction is enough).  Bits past n in the last
+// word are ignored.
+constexpr int kOverlapNT = 1024;
+__global__ void __launch_bounds__(kOverlapNT) mask_overlap_kernel(const uint32_t *a, const uint32_t *b, int64_t n,
+                                                                  int64_t *out) {
+    __shared__ uint64_t tmp[kOverlapNT / 64 + 1];
+    const int64_t nw = (n + 31) / 32;
+    const uint32_t tail = (n & 31) ? ((1u << (n & 31)) - 1u) : 0xffffffffu;
+    uint64_t ca = 0, cb = 0, cab = 0;
+    for (int64_t w = threadIdx.x; w < nw; w += kOverlapNT) {
+        const uint32_t m = w == nw - 1 ? tail : 0xffffffffu;
+        const uint32_t x = a[w] & m, y = b[w] & m;
+        ca += __popc(x);
+        cb += __popc(y);
+        cab += __popc(x & y);
+    }
+    uint64_t ta, tb, tab;
+    block_exclusive_sum<kOverlapNT>(ca, tmp, &ta);
+    block_exclusive_sum<kOverlapNT>(cb, tmp, &tb);
+    block_exclusive_sum<kOverlapNT>(cab, tmp, &tab);
+    if (threadIdx.x == 0) {
+        out[0] = (int64_t)ta;
+        out[1] = (int64_t)tb;
+        out[2] = (int64_t)tab;
+    }
+}
+
 }  // namespace
 
 size_t scan_scratch_bytes(int64_t n_max) {
@@ -323,6 +352,15 @@ hipError_t compact_bits(const uint32_t *bits, int64_t n, uint32_t *idx, int64_t 
     if (nb > 0)
         hipLaunchKernelGGL(bits_compact_kernel, dim3((unsigned)nb), dim3(kNT), 0, s, bits, n,
                            (const uint64_t *)partial, idx);
+    return hipGetLastError();
+}
+
+}  // namespace fdgs
+
+namespace fdgs {
+
+hipError_t launch_mask_overlap(const uint32_t *a, const uint32_t *b, int64_t n, int64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(mask_overlap_kernel, dim3(1), dim3(kOverlapNT), 0, s, a, b, n, out);
     return hipGetLastError();
 }
 

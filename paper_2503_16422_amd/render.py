@@ -170,6 +170,19 @@ class Context:
                                                    _ptr(bits), _ptr(idx), _ptr(count), _stream(dev)))
         return bits, idx, count
 
+    def measure_peaks(self) -> dict:
+        """Measured LDS and vector-ALU rates of the device (see fdgs_measure_peaks)."""
+        out = (ctypes.c_double * 4)()
+        _lib.check(self.lib.fdgs_measure_peaks(self.handle, out, _stream(self.device)))
+        return {"lds_broadcast_Bps": out[0], "lds_distinct_Bps": out[1], "valu_fma_lane_ops_per_s": out[2],
+                "compute_units": int(out[3])}
+
+    def mask_overlap(self, bits_a: torch.Tensor, bits_b: torch.Tensor, n: int) -> torch.Tensor:
+        """Device int64[3]: |a|, |b| and |a and b| over the first n bits."""
+        out = torch.empty((3,), dtype=torch.int64, device=bits_a.device)
+        _lib.check(self.lib.fdgs_mask_overlap(_ptr(bits_a), _ptr(bits_b), int(n), _ptr(out), _stream(bits_a.device)))
+        return out
+
     # (3) ------------------------------------------------------------------
     def render(self, model: GaussianModel, cam, t: float, cfg: Optional[_lib.RenderCfg] = None,
                idx: Optional[torch.Tensor] = None, n_idx: Optional[torch.Tensor] = None,

@@ -60,6 +60,10 @@ def test_null_context_rejected_without_gpu(lib):
     assert lib.fdgs_adam_step(None, None, None, None, None, ctypes.c_int64(0), ctypes.c_float(0.1), ctypes.c_float(0.9),
                               ctypes.c_float(0.999), ctypes.c_float(1e-8), 1, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_sh_kmeans(None, None, None, ctypes.c_int64(1), 1, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_measure_peaks(None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_mask_overlap(None, None, ctypes.c_int64(-1), None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_mask_overlap(None, None, ctypes.c_int64(10), None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_build_active_mask_noalloc(None, None, None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_create(None, 0) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_destroy(None) == _lib.FDGS_OK
 

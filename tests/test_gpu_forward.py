@@ -591,3 +591,37 @@ def test_headline_frames_in_flight_on_three_streams_match_one(ctx):
         c.close()
     for k in range(len(picks)):
         assert torch.equal(outs[k], ref[k]), picks[k]
+
+
+def test_active_ratio_and_activation_iou(ctx):
+    """The redundancy measures of Sec. 4.1 from contributed masks at single
+    timestamps: fdgs_mask_overlap counts bit-exactly (on the oracle's own sets,
+    uploaded, and on the GPU's), and the GPU's active sets lie between the
+    oracle's sure and possible sets (a ragged n exercises the last word)."""
+    sc = inputs.long_scene(29_999, seed=3)
+    views = inputs.arc_cameras(4, 4.0, 200, 150)
+    model = to_dev(sc)
+    st = oracle_settings()
+    n = sc.n
+    sets = {}
+    for t in (0.3, 0.5):
+        bits, idx, count = ctx.build_active_mask(model, [], t, t, _lib.MASK_CONTRIBUTED, views)
+        sure, maybe = omask.contributed_keep(sc.arrays(), views, (t,), st)
+        got = np.zeros(n, dtype=bool)
+        got[idx[:int(count.item())].cpu().numpy().view(np.uint32)] = True
+        assert np.all(got[sure]) and np.all(maybe[got])
+        sets[t] = (bits, got, sure, maybe)
+    (b0, g0, s0, m0), (b1, g1, s1, m1) = sets[0.3], sets[0.5]
+    out = ctx.mask_overlap(b0, b1, n).cpu().numpy()
+    assert list(out) == [int(g0.sum()), int(g1.sum()), int((g0 & g1).sum())]
+    # the counting kernel on the oracle's sets, uploaded
+    dev = lambda keep: torch.from_numpy(omask.pack_bits(keep).view(np.int32)).cuda()
+    for a, b in ((s0, s1), (m0, m1), (s0, m1)):
+        out = ctx.mask_overlap(dev(a), dev(b), n).cpu().numpy()
+        assert list(out) == [int(a.sum()), int(b.sum()), int((a & b).sum())]
+    ratio = g1.sum() / n
+    iou = (g0 & g1).sum() / (g0 | g1).sum()
+    assert s1.sum() / n <= ratio <= m1.sum() / n
+    assert 0.0 < iou < 1.0
+    print(f"active ratio at t=0.5: {ratio:.4f} (oracle {s1.sum() / n:.4f}..{m1.sum() / n:.4f}); "
+          f"IoU(0.3, 0.5) {iou:.4f}")
