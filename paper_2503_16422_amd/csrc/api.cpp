@@ -328,6 +328,8 @@ fdgs_status check_cfg(const fdgs_render_cfg *cfg, const char *fn) {
         !((cfg->batch == 512 || cfg->batch == 1024) && cfg->tile_w == 32 && cfg->tile_h == 32))
         return fail(FDGS_ERR_INVALID_ARG, "%s: batch %d not one of 64, 128, 256 (or 512 with 32x32 tiles)", fn,
                     cfg->batch);
+    if (cfg->schedule != 0 && cfg->schedule != 1)
+        return fail(FDGS_ERR_INVALID_ARG, "%s: schedule %d not one of 0, 1", fn, cfg->schedule);
     if (cfg->pixels_per_thread != 0 && cfg->pixels_per_thread != 1 && cfg->pixels_per_thread != 2 &&
         cfg->pixels_per_thread != 4)
         return fail(FDGS_ERR_INVALID_ARG, "%s: pixels_per_thread %d not one of 0, 1, 2, 4", fn,

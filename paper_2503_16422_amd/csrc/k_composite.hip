@@ -183,12 +183,21 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
             // several pixels: select-based updates, no branches or lane masks per
             // pixel, and control flow uniform over the wavefront (lanes whose pixels
             // stopped run along with w = 0), so the wavefront sums see every lane
-            auto blend = [&](int k) {
+            // alpha of record k at the thread's pixels (clamped to the float with bit
+            // pattern cap: alpha_max, or 0 to make the record a no-op)
+            auto alphas = [&](int k, float (&al)[PPT], uint32_t cap) {
                 const float4 g = s_rec[3 * k];
                 const float4 h = s_rec[3 * k + 1];
-                const float cb = s_rec[3 * k + 2].x;
                 const float dx = fx - g.x;
                 const float A = exp2_col_a(g.w, h.x, dx), B = exp2_col_t(g.y, g.z, fx);
+#pragma unroll
+                for (int p = 0; p < PPT; ++p)
+                    al[p] = clamp_alpha(__builtin_amdgcn_exp2f(exp2_at(h.y, A, B, fy[p])), cap);
+            };
+            // blend record k with those alphas (counted: whether it is an evaluated pair)
+            auto apply = [&](int k, const float (&al)[PPT], bool counted) {
+                const float4 h = s_rec[3 * k + 1];
+                const float cb = s_rec[3 * k + 2].x;
                 const uint32_t pos = base + k - start + 1;
                 bool blended = false;
                 float wsum = 0.0f;
@@ -199,8 +208,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     // transmittance would fall below thr.  The two conditions combine
                     // as lane masks, and the weight alpha T is the drop of T, so a
                     // skipped or stopped pair costs no select of its own
-                    const float e = exp2_at(h.y, A, B, fy[p]);
-                    const float alpha = clamp_alpha(__builtin_amdgcn_exp2f(e), amax_bits);
+                    const float alpha = al[p];
                     const float test = after(T[p], alpha);
                     const bool hit = alpha >= amin;
                     const bool ok = hit && test >= thr[p];
@@ -209,7 +217,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     C1[p] = fmaf(h.w, w, C1[p]);
                     C2[p] = fmaf(cb, w, C2[p]);
                     if constexpr (LAST) last[p] = ok ? pos : last[p];
-                    if constexpr (COUNT) stop[p] += thr[p] < kInf ? 1u : 0u;
+                    if constexpr (COUNT) stop[p] += (counted && thr[p] < kInf) ? 1u : 0u;
                     T[p] -= w;
                     thr[p] = hit != ok ? kInf : thr[p];   // alpha reached alpha_min, T would fall below thr
                     if constexpr (MARK) blended = blended || ok;
@@ -224,6 +232,17 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     const uint64_t m = __ballot(blended);
                     if (m != 0ull && lane == __builtin_ctzll(m)) a.contrib[__float_as_uint(s_rec[3 * k + 2].y)] = 1;
                 }
+            };
+            // two records per step: both alphas first (they do not depend on the
+            // transmittance), so the second record's LDS reads and exponentials
+            // overlap the first's blend.  With one record left the second is the
+            // same record with every alpha 0, which changes nothing.
+            auto blend2 = [&](int k1, int k2, bool two) {
+                float a1[PPT], a2[PPT];
+                alphas(k1, a1, amax_bits);
+                alphas(k2, a2, two ? amax_bits : 0u);
+                apply(k1, a1, true);
+                apply(k2, a2, two);
             };
             // whether some pixel of the wavefront is still live
             auto live = [&]() {
@@ -242,9 +261,14 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     uint64_t bits = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(word >> 32)) << 32) |
                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)word);
                     while (bits != 0ull) {
-                        blend(c + (int)__builtin_ctzll(bits));
+                        const int k1 = c + (int)__builtin_ctzll(bits);
                         bits &= bits - 1ull;
-                        if (++since == 8) {
+                        const bool two = bits != 0ull;
+                        const int k2 = two ? c + (int)__builtin_ctzll(bits) : k1;
+                        bits &= bits - (two ? 1ull : 0ull);
+                        blend2(k1, k2, two);
+                        since += 2;
+                        if (since >= 8) {
                             since = 0;
                             if (!live()) {
                                 more = false;
@@ -257,7 +281,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 // groups of 8 records, leaving the batch once no pixel of the wavefront is live
                 for (int k0 = 0; k0 < cnt; k0 += 8) {
                     const int kn = min(cnt, k0 + 8);
-                    for (int k = k0; k < kn; ++k) blend(k);
+                    for (int k = k0; k < kn; k += 2) blend2(k, min(k + 1, kn - 1), k + 1 < kn);
                     if (!live()) break;
                 }
             }
