@@ -609,23 +609,6 @@ fdgs_status fdgs_build_active_mask_noalloc(const fdgs_model *model, const fdgs_m
 
 namespace {
 
-// Cell marks in the tile keys for the compositor layout of this
-// configuration: cells of cell_w x cell_h pixels, one per wavefront (16
-// pixels wide where the tile allows, 64 x pixels-per-thread pixels); only
-// with tile culling, several pixels per thread, several cells per tile, and
-// (view, tile) numbers that leave the top 8 key bits free.
-void set_cell_marks(RenderParams *rp, int32_t ppt, int64_t n_keys) {
-    const int tw = rp->tile_w, th = rp->tile_h;
-    if (tw * th == 64) ppt = 1;   // 8x8 tiles: one pixel per thread
-    const int cw = (tw >= 16 && th >= 4 * ppt) ? 16 : tw;
-    const int ch = 64 * ppt / cw;
-    const int nw = (tw / cw) * (th / ch);
-    if (rp->tile_cull && ppt > 1 && nw > 1 && nw <= 8 && th / ch <= 4 && n_keys <= (int64_t)kTileKeyMask + 1) {
-        rp->cell_w = cw;
-        rp->cell_h = ch;
-    }
-}
-
 RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
     RenderParams rp;
     rp.tile_w = cfg->tile_w;
@@ -640,7 +623,6 @@ RenderParams make_params(const fdgs_render_cfg *cfg, int32_t W, int32_t H) {
     rp.temporal_cull = cfg->temporal_cull ? 1 : 0;
     rp.tile_cull = cfg->tile_cull ? 1 : 0;
     rp.vanilla_level = 2.0 * std::log(1.0 / (double)cfg->alpha_min) * (1.0 + 1e-4) + 1e-4;
-    rp.cell_w = rp.cell_h = 0;
     return rp;
 }
 
@@ -654,12 +636,11 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
                         float *out_rgb, float *out_T, bool need_state, hipStream_t stream, uint8_t *contrib,
                         float *weight) {
     const char *fn = "fdgs_render";
-    RenderParams rp = make_params(cfg, W, H);
+    const RenderParams rp = make_params(cfg, W, H);
     const int64_t tiles_per_view = (int64_t)rp.tiles_x * rp.tiles_y;
     const int64_t n_keys = tiles_per_view * V;
     if (n_keys >= (int64_t(1) << 31)) return fail(FDGS_ERR_INVALID_ARG, "%s: too many tiles x views", fn);
     const int32_t ppt = cfg->pixels_per_thread ? cfg->pixels_per_thread : kDefaultPpt;
-    set_cell_marks(&rp, ppt, n_keys);
     const int64_t n_max = n_total;
     const int64_t npx = (int64_t)W * H;
 
@@ -779,7 +760,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     {
         StageTimer tm(ctx, FDGS_STAGE_RANGES, stream);
         HIP_TRY(launch_tile_ranges(S->sorted_keys, counts + 1, capacity, (int32_t)n_keys, S->ranges.as<uint32_t>(),
-                                   stream, rp.cell_w > 0 ? kTileKeyMask : 0xffffffffu));
+                                   stream));
     }
     float *T_out = need_state ? S->T_final.as<float>() : out_T;
     uint64_t *acc = nullptr;
@@ -791,7 +772,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     {
         StageTimer tm(ctx, FDGS_STAGE_COMPOSITE, stream);
         HIP_TRY(launch_composite(rp, W, H, V, cfg->batch, S->ranges.as<uint32_t>(), S->sorted_ids, S->rec.as<Rec2D>(),
-                                 S->sorted_keys, out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
+                                 out_rgb, T_out, need_state ? S->n_contrib.as<uint32_t>() : nullptr,
                                  acc && ctx->prof == 2 ? acc + 3 : nullptr,
                                  ppt,
                                  cfg->schedule ? S->sched.as<uint32_t>() : nullptr, contrib, weight, stream));
@@ -1109,7 +1090,6 @@ fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *
         StageTimer tm(ctx, FDGS_STAGE_BWD_COMPOSITE, stream);
         HIP_TRY(launch_fill_u32(S->g2d.as<uint32_t>(), 9 * std::max<int64_t>(S->n_max, 1), 0u, stream));
         HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ranges.as<uint32_t>(), S->sorted_ids,
-                                          S->sorted_keys,
                                           S->rec.as<Rec2D>(), S->T_final.as<float>(), S->n_contrib.as<uint32_t>(),
                                           dL_drgb, S->g2d.as<float>(), S->n_max, stream));
     }

@@ -116,7 +116,7 @@ hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, cons
 hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, const int64_t *n_dev,
                              int64_t n_max, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
-                              int32_t n_tiles, uint32_t *ranges, hipStream_t s, uint32_t key_mask = 0xffffffffu);
+                              int32_t n_tiles, uint32_t *ranges, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 // *out = number of 32-bit words where a and b differ.
@@ -136,7 +136,7 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 // blends; weight (optional): weight[id] += the entry's summed blend weights
 // alpha T (state and counters are not recorded in either case).
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
-                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const uint32_t *keys,
+                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
                             uint64_t *pair_counter, int32_t pixels_per_thread, uint32_t *sched,
                             uint8_t *contrib, float *weight, hipStream_t s);
@@ -152,8 +152,7 @@ hipError_t launch_mask_overlap(const uint32_t *a, const uint32_t *b, int64_t n, 
 
 // Backward.
 hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
-                                     const uint32_t *ranges, const uint32_t *ids, const uint32_t *keys,
-                                     const Rec2D *rec,
+                                     const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                                      const float *T_final, const uint32_t *n_contrib,
                                      const float *dL_drgb, float *g2d, int64_t n_proc_max,
                                      hipStream_t s);

@@ -31,7 +31,6 @@ struct CompArgs {
     int32_t W, H;
     const uint32_t *ranges;
     const uint32_t *ids;
-    const uint32_t *keys;        // sorted tile keys (cell marks in the top bits when rp.cell_w > 0)
     const Rec2D *rec;
     float *out_rgb;
     float *out_T;
@@ -66,8 +65,6 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     // pixels per thread; a single-pixel thread branches per pixel instead)
     constexpr bool kBits = C::NW > 1 && PPT > 1;
     const bool cull = a.rp.tile_cull != 0;   // without tile culling every record reaches every cell
-    // the emission marked the cells of this layout in the keys
-    const bool marks = a.rp.cell_w == C::CW && a.rp.cell_h == C::CH;
     constexpr int kWords = BATCH / 64;
     __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
     const int n_tiles = a.rp.tiles_x * a.rp.tiles_y;
@@ -129,9 +126,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 const Rec2D r = a.rec[id];
                 const ExpRec q = stage_exp(r, ox, oy);
                 if constexpr (kBits) {
-                    if (cull)
-                        cells = marks ? a.keys[base + k] >> kCellMarkShift
-                                      : reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
+                    if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
                 }
                 s_rec[3 * k] = make_float4(q.gx, q.s, q.c0, q.kx);
                 s_rec[3 * k + 1] = make_float4(q.lo, q.q, r.c.x, r.c.y);
@@ -431,14 +426,14 @@ void launch_fwd(const CompArgs &a, int n_tiles, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_t V, int32_t batch,
-                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec, const uint32_t *keys,
+                            const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                             float *out_rgb, float *out_T, uint32_t *n_contrib,
                             uint64_t *pair_counter, int32_t ppt, uint32_t *sched, uint8_t *contrib,
                             float *weight, hipStream_t s) {
     if (ppt != 1 && ppt != 2 && ppt != 4) return hipErrorInvalidValue;
     const int n_tiles = rp.tiles_x * rp.tiles_y * V;
     const bool side = contrib || weight;   // visibility or score pass: no state, no counters
-    CompArgs a{rp, W, H, ranges, ids, keys, rec, out_rgb, out_T, side ? nullptr : n_contrib,
+    CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, side ? nullptr : n_contrib,
                side ? nullptr : reinterpret_cast<unsigned long long *>(pair_counter), ppt, V,
                sched, sched ? sched + n_tiles : nullptr, n_tiles, contrib, contrib ? nullptr : weight};
     if (sched) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderNT), 0, s, ranges, n_tiles, sched,

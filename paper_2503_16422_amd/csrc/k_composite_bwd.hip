@@ -16,7 +16,6 @@ struct BwdArgs {
     int32_t W, H;
     const uint32_t *ranges;
     const uint32_t *ids;
-    const uint32_t *keys;   // sorted tile keys (cell marks in the top bits when rp.cell_w > 0)
     const Rec2D *rec;
     const float *T_final;
     const uint32_t *n_contrib;
@@ -47,8 +46,6 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     constexpr int kWords = BATCH / 64;
     __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
     const bool cull = a.rp.tile_cull != 0;
-    // the forward's emission marked the cells of this layout in the keys
-    const bool marks = a.rp.cell_w == C::CW && a.rp.cell_h == C::CH;
     __shared__ float4 s_xy[BATCH];    // centre (block-centred), log2 opacity, 1 / opacity
     __shared__ float4 s_ex[BATCH];    // s, c0, kx, q: the exponent as the forward stages it
     __shared__ float4 s_rgb[BATCH];
@@ -113,9 +110,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                 s_rgb[k] = r.c;
                 s_id[k] = id;
                 if constexpr (kBits) {
-                    if (cull)
-                        cells = marks ? a.keys[lo + k] >> kCellMarkShift
-                                      : reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
+                    if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
                 }
             }
             if (kBits && cull) {
@@ -236,12 +231,11 @@ void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
-                                     const uint32_t *ranges, const uint32_t *ids, const uint32_t *keys,
-                                     const Rec2D *rec,
+                                     const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                                      const float *T_final, const uint32_t *n_contrib,
                                      const float *dL_drgb, float *g2d, int64_t /*n_proc_max*/,
                                      hipStream_t s) {
-    BwdArgs a{rp, W, H, ranges, ids, keys, rec, T_final, n_contrib, dL_drgb, g2d};
+    BwdArgs a{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d};
     const int n_tiles = rp.tiles_x * rp.tiles_y;
     FDGS_DISPATCH(launch_bwd, a);
     return hipGetLastError();

@@ -264,7 +264,6 @@ __global__ void fix_ties_kernel(uint32_t *keys32, uint32_t *vals, const uint64_t
 // counts hold.
 constexpr int kDupNT = 256;
 constexpr int kDupE = 2048;
-constexpr int kMaxBands = 4;   // bands of cell rows per tile (cell marks)
 
 __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order, const uint64_t *offsets,
                                                            const int32_t *rect, const Rec2D *rec,
@@ -335,9 +334,6 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
         for (uint32_t row0 = 0; row0 < n_rows_total; row0 += kDupNT) {
             const uint32_t rho = row0 + (uint32_t)t;
             uint32_t n = 0, key0 = 0, rid = 0;
-            int tx0 = 0;
-            bool band_ok[kMaxBands];
-            int band_p0[kMaxBands], band_p1[kMaxBands];
             if (rho < n_rows_total) {
                 int a = 0, b = cnt - 1;                // largest Gaussian with s_rbase <= rho
                 while (a < b) {
@@ -350,20 +346,6 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
                 if (tile_row_span(s_ell[a], r, ty, rp.tile_w, rp.tile_h, &c0, &c1)) {
                     n = (uint32_t)(c1 - c0 + 1);
                     key0 = s_base[a] + (uint32_t)(ty * rp.tiles_x + c0);
-                    tx0 = c0;
-                    if (rp.cell_w > 0) {
-                        // the columns each band of cell rows reaches over the row's tiles
-                        // (the cells' test, evaluated once for all tiles of the row)
-                        const int x_lo = c0 * rp.tile_w, x_hi = (c1 + 1) * rp.tile_w - 1;
-#pragma unroll
-                        for (int b = 0; b < kMaxBands; ++b) {
-                            band_ok[b] = false;
-                            const int r0 = ty * rp.tile_h + b * rp.cell_h;
-                            if (b * rp.cell_h < rp.tile_h)
-                                band_ok[b] = ellipse_band_columns(s_ell[a], r0, r0 + rp.cell_h - 1, x_lo, x_hi,
-                                                                  &band_p0[b], &band_p1[b]);
-                        }
-                    }
                 }
                 rid = s_id[a];
             }
@@ -373,22 +355,7 @@ __global__ void __launch_bounds__(kDupNT) duplicate_kernel(const uint32_t *order
             const int64_t r0 = (int64_t)carry + pos;
             const int64_t ka = max(r0, e_lo), kb = min(r0 + (int64_t)n, e_hi);
             for (int64_t k = ka; k < kb; ++k) {
-                uint32_t key = key0 + (uint32_t)(k - r0);
-                if (rp.cell_w > 0) {
-                    const int x0 = (tx0 + (int)(k - r0)) * rp.tile_w;
-                    const int cx_n = rp.tile_w / rp.cell_w;
-                    uint32_t m = 0;
-#pragma unroll
-                    for (int b = 0; b < kMaxBands; ++b) {
-                        if (!band_ok[b]) continue;
-                        for (int cx = 0; cx < cx_n; ++cx) {
-                            const int cs = x0 + cx * rp.cell_w;
-                            if (band_p0[b] <= cs + rp.cell_w - 1 && band_p1[b] >= cs) m |= 1u << (b * cx_n + cx);
-                        }
-                    }
-                    key |= m << kCellMarkShift;
-                }
-                s_key[k - e_lo] = key;
+                s_key[k - e_lo] = key0 + (uint32_t)(k - r0);
                 s_val[k - e_lo] = rid;
             }
             carry += chunk_total;
@@ -446,19 +413,19 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
 // one streaming read of the keys.  With long lists (few tiles, many
 // instances) a thread per tile binary-searches its two bounds instead.
 __global__ void ranges_boundary_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max, int32_t n_tiles,
-                                       uint32_t key_mask, uint32_t *ranges) {
+                                       uint32_t *ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = count_of(n_dev, n_max);
     if (i > n) return;
-    const int64_t prev = i == 0 ? -1 : (int64_t)min(keys[i - 1] & key_mask, (uint32_t)n_tiles);
-    const int64_t next = i == n ? (int64_t)n_tiles : (int64_t)min(keys[i] & key_mask, (uint32_t)n_tiles);
+    const int64_t prev = i == 0 ? -1 : (int64_t)min(keys[i - 1], (uint32_t)n_tiles);
+    const int64_t next = i == n ? (int64_t)n_tiles : (int64_t)min(keys[i], (uint32_t)n_tiles);
     if (prev == next) return;
     for (int64_t t = prev + 1; t <= next && t < n_tiles; ++t) ranges[2 * t] = (uint32_t)i;
     for (int64_t t = max(prev, (int64_t)0); t < next; ++t) ranges[2 * t + 1] = (uint32_t)i;
 }
 
 __global__ void ranges_search_kernel(const uint32_t *keys, const int64_t *n_dev, int64_t n_max, int32_t n_tiles,
-                                     uint32_t key_mask, uint32_t *ranges) {
+                                     uint32_t *ranges) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
     const int64_t n = count_of(n_dev, n_max);
@@ -466,7 +433,7 @@ __global__ void ranges_search_kernel(const uint32_t *keys, const int64_t *n_dev,
         int64_t lo = 0, hi = n;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
-            if ((keys[mid] & key_mask) < key) lo = mid + 1; else hi = mid;
+            if (keys[mid] < key) lo = mid + 1; else hi = mid;
         }
         return lo;
     };
@@ -625,14 +592,14 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 }
 
 hipError_t launch_tile_ranges(const uint32_t *tile_keys, const int64_t *n_inst_dev, int64_t n_max,
-                              int32_t n_tiles, uint32_t *ranges, hipStream_t s, uint32_t key_mask) {
+                              int32_t n_tiles, uint32_t *ranges, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     if (n_max > (int64_t)kRangesSearchAbove * n_tiles)
         hipLaunchKernelGGL(ranges_search_kernel, dim3(blocks_for(n_tiles, 256)), dim3(256), 0, s, tile_keys,
-                           n_inst_dev, n_max, n_tiles, key_mask, ranges);
+                           n_inst_dev, n_max, n_tiles, ranges);
     else
         hipLaunchKernelGGL(ranges_boundary_kernel, dim3(blocks_for(n_max + 1, 256)), dim3(256), 0, s, tile_keys,
-                           n_inst_dev, n_max, n_tiles, key_mask, ranges);
+                           n_inst_dev, n_max, n_tiles, ranges);
     return hipGetLastError();
 }
 

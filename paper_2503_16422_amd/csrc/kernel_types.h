@@ -45,15 +45,6 @@ struct RenderParams {
     int32_t temporal_cull;
     int32_t tile_cull;      // list a record only in the tiles its ellipse reaches
     double vanilla_level;   // cut level without opacity culling, incl. margin
-    // Cell marks: when cell_w > 0 the tile-key emission sets bit 24 + c of an
-    // instance's key for each cell c (cell_w x cell_h pixels, numbered row by
-    // row within the tile) that the record's footprint ellipse reaches; the
-    // compositors read them instead of testing the ellipse themselves.
-    int32_t cell_w, cell_h;
 };
-
-// Bits of a tile key that hold the (view, tile) number when cell marks are set.
-constexpr int kCellMarkShift = 24;
-constexpr uint32_t kTileKeyMask = (1u << kCellMarkShift) - 1u;
 
 }  // namespace fdgs

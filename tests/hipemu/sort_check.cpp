@@ -1,10 +1,8 @@
 // Host run of the tile binning kernels (paper_2503_16422_amd/csrc/k_sort.hip)
 // through the emulation header: tile-key emission by instance windows (with
-// and without ellipse culling, and with the compositor's cell marks in the top
-// key bits) and its first-digit histogram, the stable radix sort by tile using
-// that histogram, and both tile-range kernels.  Expected values come from
-// plain host loops over the same row spans and, for the marks, a per-tile test
-// of every band of cell rows.
+// and without ellipse culling) and its first-digit histogram, the stable radix
+// sort by tile using that histogram, and both tile-range kernels.  Expected
+// values come from plain host loops over the same row spans.
 #include "hip/hip_runtime.h"
 #include "k_sort_host.inc"
 #include <cstdio>
@@ -23,9 +21,8 @@ int main(int argc, char **argv) {
     const bool full = argc > 1 && std::string(argv[1]) == "full";
     std::mt19937_64 rng(9);
     auto U = [&](double a, double b) { return std::uniform_real_distribution<double>(a, b)(rng); };
-    for (int trial = full ? 0 : 1; trial < 3; ++trial) {
-        // trial 2: 32x32 tiles with marks for cells of 16x8 pixels (4 bands of 2 cells)
-        const int W = 200, H = 150, tw = trial == 2 ? 32 : 8, th = trial == 2 ? 32 : 8;
+    for (int trial = full ? 0 : 1; trial < 2; ++trial) {
+        const int W = 200, H = 150, tw = 8, th = 8;
         RenderParams rp{};
         rp.tile_w = tw;
         rp.tile_h = th;
@@ -35,10 +32,7 @@ int main(int argc, char **argv) {
         rp.alpha_max = 0.99f;
         rp.t_min = 1e-4f;
         rp.temporal_cull = 1;
-        rp.tile_cull = trial != 1;
-        rp.cell_w = trial == 2 ? 16 : 0;
-        rp.cell_h = trial == 2 ? 8 : 0;
-        const uint32_t key_mask = trial == 2 ? kTileKeyMask : 0xffffffffu;
+        rp.tile_cull = trial == 0;
         rp.vanilla_level = 2.0 * std::log(255.0) * (1 + 1e-4) + 1e-4;
         const int64_t n_vis = trial == 0 ? 700 : 2000;
         std::vector<Rec2D> rec(n_vis);
@@ -72,23 +66,7 @@ int main(int argc, char **argv) {
                 int c0, c1;
                 if (!tile_row_span(e, r, ty, tw, th, &c0, &c1)) continue;
                 for (int cx = c0; cx <= c1; ++cx) {
-                    uint32_t key = (uint32_t)(ty * rp.tiles_x + cx);
-                    if (rp.cell_w > 0) {
-                        // per tile: the columns of each band of cell rows within the tile
-                        uint32_t m = 0;
-                        const int ncx = tw / rp.cell_w;
-                        for (int b = 0; b < th / rp.cell_h; ++b) {
-                            const int r0 = ty * th + b * rp.cell_h;
-                            int p0, p1;
-                            if (!ellipse_band_columns(e, r0, r0 + rp.cell_h - 1, cx * tw, cx * tw + tw - 1, &p0, &p1))
-                                continue;
-                            for (int k = 0; k < ncx; ++k) {
-                                const int cs = cx * tw + k * rp.cell_w;
-                                if (p0 <= cs + rp.cell_w - 1 && p1 >= cs) m |= 1u << (b * ncx + k);
-                            }
-                        }
-                        key |= m << kCellMarkShift;
-                    }
+                    const uint32_t key = (uint32_t)(ty * rp.tiles_x + cx);
                     ekey.push_back(key);
                     eid.push_back(id);
                 }
@@ -135,16 +113,11 @@ int main(int argc, char **argv) {
         // expected: stable sort of the emission by tile
         std::vector<int64_t> perm(n_inst);
         for (int64_t i = 0; i < n_inst; ++i) perm[i] = i;
-        std::stable_sort(perm.begin(), perm.end(),
-                         [&](int64_t a, int64_t b) { return (ekey[a] & key_mask) < (ekey[b] & key_mask); });
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return ekey[a] < ekey[b]; });
         for (int64_t i = 0; i < n_inst; ++i)
             if (sk[i] != ekey[perm[i]] || si[i] != eid[perm[i]]) return fail("stable tile sort");
         std::vector<uint32_t> ranges(2 * n_tiles, 0xffffffffu);
-        std::vector<uint32_t> tile_of(n_inst);
-        for (int64_t i = 0; i < n_inst; ++i) tile_of[i] = sk[i] & key_mask;
-        uint32_t marked = 0;
-        for (int64_t i = 0; i < n_inst; ++i) marked += (sk[i] >> kCellMarkShift) != 0;
-        if (trial == 2 && marked != n_inst) return fail("an instance without a reached cell");
+        std::vector<uint32_t> tile_of(sk, sk + n_inst);
         // both range kernels: the boundary scan, and the binary searches (forced by a larger n_max)
         for (int search = 0; search < 2; ++search) {
             std::vector<uint32_t> ranges(2 * n_tiles, 0xffffffffu);
@@ -152,9 +125,9 @@ int main(int argc, char **argv) {
                 std::vector<uint32_t> big(sk, sk + n_inst);
                 big.resize((size_t)n_tiles * 2049 + 1, 0xffffffffu);
                 int64_t n_big = n_inst;
-                launch_tile_ranges(big.data(), &n_big, (int64_t)big.size(), n_tiles, ranges.data(), nullptr, key_mask);
+                launch_tile_ranges(big.data(), &n_big, (int64_t)big.size(), n_tiles, ranges.data(), nullptr);
             } else {
-                launch_tile_ranges(sk, &n_inst_dev, capacity, n_tiles, ranges.data(), nullptr, key_mask);
+                launch_tile_ranges(sk, &n_inst_dev, capacity, n_tiles, ranges.data(), nullptr);
             }
             for (int t = 0; t < n_tiles; ++t) {
                 const uint32_t lo = (uint32_t)(std::lower_bound(tile_of.begin(), tile_of.end(), (uint32_t)t) - tile_of.begin());
