@@ -164,7 +164,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     C0[0] = fmaf(h.z, w, C0[0]);
                     C1[0] = fmaf(h.w, w, C1[0]);
                     C2[0] = fmaf(s_rec[3 * k + 2].x, w, C2[0]);
-                    T[0] -= w;
+                    T[0] = test;
                     if constexpr (LAST) last[0] = pos;
                     if constexpr (MARK) {
                         // lanes here blended record k: the lowest one flags it
@@ -201,19 +201,21 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     // blend when alpha reaches alpha_min and the pixel keeps at least
                     // thr (t_min while live); stop when alpha reaches alpha_min but the
                     // transmittance would fall below thr.  The two conditions combine
-                    // as lane masks, and the weight alpha T is the drop of T, so a
-                    // skipped or stopped pair costs no select of its own
+                    // as lane masks; the new transmittance is one select and the
+                    // weight alpha T is its drop, so a skipped or stopped pair
+                    // (weight 0) costs nothing more
                     const float alpha = al[p];
                     const float test = after(T[p], alpha);
                     const bool hit = alpha >= amin;
                     const bool ok = hit && test >= thr[p];
-                    const float w = ok ? T[p] - test : 0.0f;
+                    const float Tn = ok ? test : T[p];
+                    const float w = T[p] - Tn;
                     C0[p] = fmaf(h.z, w, C0[p]);
                     C1[p] = fmaf(h.w, w, C1[p]);
                     C2[p] = fmaf(cb, w, C2[p]);
                     if constexpr (LAST) last[p] = ok ? pos : last[p];
                     if constexpr (COUNT) stop[p] += (counted && thr[p] < kInf) ? 1u : 0u;
-                    T[p] -= w;
+                    T[p] = Tn;
                     thr[p] = hit != ok ? kInf : thr[p];   // alpha reached alpha_min, T would fall below thr
                     if constexpr (MARK) blended = blended || ok;
                     if constexpr (WEIGHT) wsum += w;
@@ -257,10 +259,10 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)word);
                     while (bits != 0ull) {
                         const int k1 = c + (int)__builtin_ctzll(bits);
-                        bits &= bits - 1ull;
-                        const bool two = bits != 0ull;
-                        const int k2 = two ? c + (int)__builtin_ctzll(bits) : k1;
-                        bits &= bits - (two ? 1ull : 0ull);
+                        const uint64_t rest = bits & (bits - 1ull);   // without k1
+                        const bool two = rest != 0ull;
+                        const int k2 = two ? c + (int)__builtin_ctzll(rest) : k1;
+                        bits = rest & (rest - 1ull);                  // 0 when rest is 0
                         blend2(k1, k2, two);
                         since += 2;
                         if (since >= 8) {
