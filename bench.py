@@ -350,14 +350,16 @@ def finetune_timing(ctx, scene, cams, frames, masks, frame_window, cfg, steps=40
 
 # tile shapes and LDS batches tried for the fwd+bwd loop (the forward autotuner
 # times forwards only; here the adjoint decides as much)
-FWD_BWD_TILES = ((16, 16, 128), (16, 16, 256), (32, 16, 256), (32, 32, 256))
+# tile shape, LDS batch and pixels per thread (the adjoint takes the forward's 2 or 4)
+FWD_BWD_TILES = ((16, 16, 128, 2), (16, 16, 256, 2), (32, 16, 256, 2), (32, 32, 256, 2), (16, 16, 256, 4),
+                 (32, 16, 256, 4), (32, 32, 256, 4))
 
 
-def fwd_bwd(ctx, steps, warmup):
+def fwd_bwd(ctx, steps, warmup, streams=3):
     import numpy as np
     import torch
     from paper_2503_16422_amd import _lib, inputs
-    from paper_2503_16422_amd.render import GaussianModel
+    from paper_2503_16422_amd.render import Context, GaussianModel, forward_backward_views
     sc = inputs.dense_scene(500_000, seed=0)
     tgt = inputs.dense_scene(500_000, seed=1)
     cams = inputs.arc_cameras(20, 4.0, 1352, 1014)
@@ -394,14 +396,43 @@ def fwd_bwd(ctx, steps, warmup):
         return (time.perf_counter() - t0) * 1e3 / n
 
     sweep = {}
-    for tw, th, b in FWD_BWD_TILES:
-        cfg = _lib.default_cfg(tile_w=tw, tile_h=th, batch=b)
-        sweep[f"{tw}x{th}/b{b}"] = round(timed(cfg, 4, 2), 3)
+    cfgs = {}
+    for tw, th, b, p in FWD_BWD_TILES:
+        key = f"{tw}x{th}/b{b}/p{p}"
+        cfgs[key] = _lib.default_cfg(tile_w=tw, tile_h=th, batch=b, pixels_per_thread=p)
+        sweep[key] = round(timed(cfgs[key], 4, 2), 3)
         release()
     best = min(sweep, key=sweep.get)
-    tw, th = (int(x) for x in best.split("/")[0].split("x"))
-    cfg = _lib.default_cfg(tile_w=tw, tile_h=th, batch=int(best.split("/b")[1]))
-    ms = timed(cfg, steps, warmup)
+    cfg = cfgs[best]
+    ms_one = timed(cfg, steps, warmup)
+    # the same iteration with consecutive views dealt round-robin to `streams`
+    # contexts (one stream each): a view's forward runs beside the previous
+    # view's adjoint; the adjoints stay in view order (identical gradients)
+    ms = ms_one
+    if streams > 1:
+        ctxs = [ctx] + [Context(0) for _ in range(streams - 1)]
+        pviews = [(cams[c], t, None, None) for c, t in views]
+        pstates = [None] * len(views)
+
+        def pstep():
+            nonlocal pstates
+            for g in grads.values():
+                g.zero_()
+            pstates = forward_backward_views(ctxs, model, pviews, cfg, lambda v, rgb: rgb - targets[v], grads,
+                                             pstates)
+
+        for _ in range(warmup):
+            pstep()
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pstep()
+        sync()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        for st in pstates:
+            st.release()
+        for c in ctxs[1:]:
+            c.close()
     ctx.profile(True, count_pairs=True)
     for _ in range(3):
         step(cfg)
@@ -416,7 +447,8 @@ def fwd_bwd(ctx, steps, warmup):
            "flops_per_pair": BWD_FLOPS_PER_PAIR,
            "achieved_TFLOPs": round(pairs * BWD_FLOPS_PER_PAIR / (bwd_ms * 1e-3) / 1e12, 3)}
     adj["frac_of_fp32_peak"] = round(adj["achieved_TFLOPs"] / FP32_PEAK_TFLOPS, 4)
-    return ms, views, stage_ms, {"chosen": best, "sweep_ms_per_iter": sweep}, adj
+    return ms, views, stage_ms, {"chosen": best, "sweep_ms_per_iter": sweep, "one_stream_ms_per_iter": round(ms_one, 3),
+                                 "streams": streams}, adj
 
 
 def batched(ctx, steps=3):
@@ -506,6 +538,8 @@ def main():
                     help="only a few dense 3M-Gaussian unfiltered frames (for profiler runs)")
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="only the forward+backward loop (500k Gaussians, 4 views; for profiler runs)")
+    ap.add_argument("--fwd-bwd-streams", type=int, default=3,
+                    help="contexts (one stream each) the fwd+bwd iteration deals its views to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -536,7 +570,7 @@ def main():
         sync()
         del a, b
     if args.fwd_bwd_only:
-        ms_iter, views, fb_stages, fb_tiles, _ = fwd_bwd(ctx, args.steps, args.warmup)
+        ms_iter, views, fb_stages, fb_tiles, _ = fwd_bwd(ctx, args.steps, args.warmup, args.fwd_bwd_streams)
         log(f"[bench] fwd+bwd {ms_iter:.2f} ms/iter; tiles {fb_tiles}; stages {json.dumps(fb_stages)}")
         return
     W, H = 1352, 1014
@@ -747,7 +781,7 @@ def main():
 
         # ---- forward + backward ------------------------------------------------------
         log("[bench] fwd+bwd: 500k Gaussians, 4 views")
-        ms_iter, views, fb_stages, fb_tiles, adj = fwd_bwd(ctx, 20, 5)
+        ms_iter, views, fb_stages, fb_tiles, adj = fwd_bwd(ctx, 20, 5, args.fwd_bwd_streams)
         extra["fwd_bwd_ms_per_iter"] = round(ms_iter, 3)
         extra["fwd_bwd_stage_ms_per_iter"] = fb_stages
         extra["fwd_bwd_adjoint_compositor"] = adj

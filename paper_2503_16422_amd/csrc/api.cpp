@@ -113,6 +113,7 @@ struct fdgs_state {
     double t = 0.0;
     RenderParams rp{};
     int32_t batch = 128;
+    int32_t ppt = 2;   // pixels per thread of the forward (the adjoint takes 4 when it did, else 2)
     int64_t n_max = 0;
     int64_t capacity = 0;
     uint32_t *sorted_ids = nullptr;   // points into tids or tids2
@@ -781,6 +782,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
         HIP_TRY(hipMemcpyAsync(out_T, S->T_final.p, sizeof(float) * npx, hipMemcpyDeviceToDevice, stream));
     S->rp = rp;
     S->batch = cfg->batch;
+    S->ppt = ppt;
     S->capacity = capacity;
     S->W = W;
     S->H = H;
@@ -1089,9 +1091,10 @@ fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *
     {
         StageTimer tm(ctx, FDGS_STAGE_BWD_COMPOSITE, stream);
         HIP_TRY(launch_fill_u32(S->g2d.as<uint32_t>(), 9 * std::max<int64_t>(S->n_max, 1), 0u, stream));
-        HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ranges.as<uint32_t>(), S->sorted_ids,
-                                          S->rec.as<Rec2D>(), S->T_final.as<float>(), S->n_contrib.as<uint32_t>(),
-                                          dL_drgb, S->g2d.as<float>(), S->n_max, stream));
+        HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ppt, S->ranges.as<uint32_t>(),
+                                          S->sorted_ids, S->rec.as<Rec2D>(), S->T_final.as<float>(),
+                                          S->n_contrib.as<uint32_t>(), dL_drgb, S->g2d.as<float>(), S->n_max,
+                                          stream));
     }
     {
         StageTimer tm(ctx, FDGS_STAGE_BWD_PREPROCESS, stream);

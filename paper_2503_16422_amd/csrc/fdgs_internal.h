@@ -151,7 +151,7 @@ hipError_t measure_peaks(float *sink, double *out, hipStream_t s);
 hipError_t launch_mask_overlap(const uint32_t *a, const uint32_t *b, int64_t n, int64_t *out, hipStream_t s);
 
 // Backward.
-hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch, int32_t ppt,
                                      const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                                      const float *T_final, const uint32_t *n_contrib,
                                      const float *dL_drgb, float *g2d, int64_t n_proc_max,

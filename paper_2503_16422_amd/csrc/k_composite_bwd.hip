@@ -273,23 +273,33 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     }
 }
 
-// Pixels per thread in the adjoint: 2 for the 256-pixel tiles, 1 for 8x8.
+// Pixels per thread in the adjoint: 1 for 8x8 tiles, else 4 when the forward
+// took 4 and 2 otherwise.
+struct BwdLaunch {
+    BwdArgs a;
+    int32_t ppt;
+};
 template <int TW, int TH, int BATCH>
-void launch_bwd(const BwdArgs &a, int n_tiles, hipStream_t s) {
-    constexpr int PPT = TW * TH > 64 ? 2 : 1;
-    hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, BATCH, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, a);
+void launch_bwd(const BwdLaunch &l, int n_tiles, hipStream_t s) {
+    if constexpr (TW * TH == 64) {
+        hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, BATCH, 1>), dim3(n_tiles), dim3(64), 0, s, l.a);
+    } else if (l.ppt == 4) {
+        hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, BATCH, 4>), dim3(n_tiles), dim3(TW * TH / 4), 0, s, l.a);
+    } else {
+        hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, BATCH, 2>), dim3(n_tiles), dim3(TW * TH / 2), 0, s, l.a);
+    }
 }
 
 }  // namespace
 
-hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch,
+hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t H, int32_t batch, int32_t ppt,
                                      const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                                      const float *T_final, const uint32_t *n_contrib,
                                      const float *dL_drgb, float *g2d, int64_t /*n_proc_max*/,
                                      hipStream_t s) {
-    BwdArgs a{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d};
+    BwdLaunch l{BwdArgs{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d}, ppt};
     const int n_tiles = rp.tiles_x * rp.tiles_y;
-    FDGS_DISPATCH(launch_bwd, a);
+    FDGS_DISPATCH(launch_bwd, l);
     return hipGetLastError();
 }
 

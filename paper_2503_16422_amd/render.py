@@ -356,6 +356,61 @@ class Context:
                 "processed": p.processed, "visible": p.visible, "instances": p.instances, "pairs": p.pairs}
 
 
+def _own_stream(ctx: Context) -> "torch.cuda.Stream":
+    """A stream of the context's own (default priority), created on first use."""
+    s = getattr(ctx, "_own_stream", None)
+    if s is None:
+        s = torch.cuda.Stream(ctx.device)
+        ctx._own_stream = s
+    return s
+
+
+def forward_backward_views(ctxs, model: GaussianModel, views, cfg: Optional[_lib.RenderCfg], loss_grad, grads,
+                           states=None):
+    """Forward pass and adjoint of several views, adding the gradients of
+    sum_v L_v into `grads` (caller-zeroed tensors in the model's layout).
+
+    views: (cam, t, idx, n_idx) per view (idx, n_idx may be None: dense).
+    loss_grad(v, rgb) returns dL_v/drgb for view v's image.  View v is rendered
+    and differentiated by ctxs[v % len(ctxs)] on a stream of that context's
+    own, so a view's forward (short launches that fill the device poorly)
+    runs beside the previous view's adjoint.  The adjoints are chained in view
+    order by events, so the gradients are added in the same order, and come out
+    the same, as in a loop over the views on one stream.  states: States to
+    reuse (one per view, each owned by the context that renders its view) or
+    None; the list of states is returned.  The work starts after everything
+    queued on the caller's current stream, and that stream waits for the last
+    adjoint before this returns."""
+    dev = ctxs[0].device
+    cur = torch.cuda.current_stream(dev)
+    begin = torch.cuda.Event()
+    begin.record(cur)
+    streams = [_own_stream(c) for c in ctxs]
+    for s in streams:
+        s.wait_event(begin)
+    states = list(states) if states is not None else [None] * len(views)
+    if len(states) != len(views):
+        raise ValueError("forward_backward_views: one state per view")
+    prev = None
+    for v, (cam, t, idx, n_idx) in enumerate(views):
+        c, s = ctxs[v % len(ctxs)], streams[v % len(ctxs)]
+        st = states[v]
+        if st is not None and st.ctx is not c:
+            raise ValueError(f"forward_backward_views: state of view {v} belongs to another context")
+        with torch.cuda.stream(s):
+            rgb, _, st = c.render(model, cam, t, cfg, idx=idx, n_idx=n_idx, keep_state=st if st is not None else True)
+            states[v] = st
+            dL = loss_grad(v, rgb)
+            if prev is not None:
+                s.wait_event(prev)
+            c.backward(st, dL, model, grads)
+            prev = torch.cuda.Event()
+            prev.record(s)
+    if prev is not None:
+        cur.wait_event(prev)
+    return states
+
+
 class Render4DGS(torch.autograd.Function):
     """rgb = Render4DGS.apply(context, cam, t, cfg, idx, n_idx, mean, log_scale, q_left, q_right,
     opacity_logit, sh).  The backward runs the library's adjoint kernels."""

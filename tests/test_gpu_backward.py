@@ -43,14 +43,23 @@ def scene_small(n, seed, grow=1.0):
     return sc
 
 
-@pytest.mark.parametrize("n,size,grow,tile,batch", [(64, 32, 1.0, (16, 16), 128), (2000, 128, 0.5, (16, 16), 128),
-                                                    (2000, 128, 0.5, (32, 16), 128), (2000, 128, 0.5, (32, 32), 128),
-                                                    (2000, 128, 0.5, (32, 32), 1024), (2000, 128, 0.5, (8, 8), 128)])
-def test_backward_matches_oracle_gradient(ctx, n, size, grow, tile, batch):
+@pytest.mark.parametrize("n,size,grow,tile,batch,ppt", [(64, 32, 1.0, (16, 16), 128, 2),
+                                                        (2000, 128, 0.5, (16, 16), 128, 2),
+                                                        (2000, 128, 0.5, (32, 16), 128, 2),
+                                                        (2000, 128, 0.5, (32, 32), 128, 2),
+                                                        (2000, 128, 0.5, (32, 32), 1024, 2),
+                                                        (2000, 128, 0.5, (8, 8), 128, 1),
+                                                        (2000, 128, 0.5, (16, 16), 256, 4),
+                                                        (2000, 128, 0.5, (32, 16), 256, 4),
+                                                        (2000, 128, 0.5, (32, 8), 128, 4),
+                                                        (2000, 100, 0.5, (32, 32), 256, 4)])
+def test_backward_matches_oracle_gradient(ctx, n, size, grow, tile, batch, ppt):
+    """The adjoint takes 2 or 4 pixels per thread after the forward's (1 for
+    8x8 tiles); the 100x100 image leaves ragged tiles."""
     from paper_2503_16422_amd.render import GaussianModel
     sc = scene_small(n, seed=3, grow=grow)
     cam = inputs.look_at_camera(0.0, 3.0, size, size)
-    cfg = _lib.default_cfg(bg=(0.1, 0.2, 0.3), tile_w=tile[0], tile_h=tile[1], batch=batch)
+    cfg = _lib.default_cfg(bg=(0.1, 0.2, 0.3), tile_w=tile[0], tile_h=tile[1], batch=batch, pixels_per_thread=ppt)
     model = GaussianModel.from_scene(sc, "cuda:0")
     rgb, _, state = ctx.render(model, cam, 0.5, cfg, keep_state=True)
     G = np.random.default_rng(0).standard_normal((3, size, size))
@@ -138,3 +147,41 @@ def test_backward_full_scene_on_crops(ctx, crop):
     for k in NAMES:
         assert torch.all(grads[k][..., dropped] == 0), k
     print(f"crop {crop}: {keep.size} Gaussians reach it; errors " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+
+
+def test_views_pipelined_over_contexts_match_one_stream(ctx):
+    """forward_backward_views over 1, 2 and 3 contexts (one stream each) adds
+    the same gradients as the views rendered and differentiated one after
+    another on one stream (up to the order of the adjoint's float atomics)."""
+    from paper_2503_16422_amd.render import Context, GaussianModel, forward_backward_views
+    sc = scene_small(3000, seed=11, grow=0.3)
+    model = GaussianModel.from_scene(sc, "cuda:0")
+    cams = inputs.arc_cameras(20, 4.0, 200, 150)
+    keep = np.sort(np.random.default_rng(4).choice(sc.n, 2100, replace=False))
+    idx = torch.from_numpy(keep.astype(np.int32)).cuda()
+    n_idx = torch.tensor([keep.size], dtype=torch.int64, device="cuda")
+    views = [(cams[c], t, i, n) for c, t, i, n in [(3, 0.2, None, None), (9, 0.5, idx, n_idx), (14, 0.71, None, None),
+                                                    (1, 0.9, idx, n_idx), (17, 0.33, None, None)]]
+    tgt = [torch.rand(3, 150, 200, device="cuda") for _ in views]
+    cfg = _lib.default_cfg()
+    ref = {k: torch.zeros_like(getattr(model, k)) for k in NAMES}
+    for v, (cam, t, i, n) in enumerate(views):
+        rgb, _, st = ctx.render(model, cam, t, cfg, idx=i, n_idx=n, keep_state=True)
+        ctx.backward(st, rgb - tgt[v], model, ref)
+        ctx.release(st)
+    torch.cuda.synchronize()
+    for n_ctx in (1, 2, 3):
+        ctxs = [ctx] + [Context(0) for _ in range(n_ctx - 1)]
+        got = {k: torch.zeros_like(getattr(model, k)) for k in NAMES}
+        states = None
+        for _ in range(2):   # the second pass reuses the states
+            for g in got.values():
+                g.zero_()
+            states = forward_backward_views(ctxs, model, views, cfg, lambda v, rgb: rgb - tgt[v], got, states)
+        torch.cuda.synchronize()
+        for st in states:
+            st.release()
+        for c in ctxs[1:]:
+            c.close()
+        for k in NAMES:
+            assert torch.allclose(got[k], ref[k], rtol=1e-5, atol=1e-6 * float(ref[k].abs().max()) + 1e-12), (n_ctx, k)
