@@ -7,8 +7,8 @@ forward path: keyframe active set (one mask per 10-frame window, built before
 timing) -> slice/project/shade -> visible compaction -> depth sort -> tile
 keys -> tile sort -> ranges -> per-tile blending.  value = frames/s over
 --steps frames, inputs resident in HBM, with consecutive frames dealt
-round-robin over --streams streams (default 3, one context and one image
-each; the one-stream rate is reported beside it).  Per-stage and roofline
+round-robin over --streams streams (default 4, one context and one image
+each, on eight hardware queues; the one-stream rate is reported beside it).  Per-stage and roofline
 timings come from a one-stream pass, where kernels do not share the GPU.
 
 Beside it on the same JSON line: the unfiltered 3M-Gaussian dense baseline,
@@ -525,10 +525,13 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--streams", type=int, default=3,
-                    help="headline frames dealt round-robin over this many streams (one context each; "
-                         "HIP gives a process 4 hardware queues by default, and the default stream, "
-                         "which builds the masks and runs the one-stream pass, holds one of them)")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="headline frames dealt round-robin over this many streams (one context each)")
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="hardware queues HIP gives this process (GPU_MAX_HW_QUEUES, set before HIP starts; "
+                         "HIP's default is 4, of which the default stream, which builds the masks and runs "
+                         "the one-stream pass, holds one: more frame streams than three then share queues); "
+                         "0 leaves the environment as it is")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the masked headline loop (for profiler runs)")
     ap.add_argument("--config", default=None,
@@ -550,6 +553,11 @@ def main():
     if args.streams < 1:
         print("--streams must be at least 1", file=sys.stderr)
         sys.exit(2)
+    if not 0 <= args.hw_queues <= 32:
+        print("--hw-queues must be in [0, 32]", file=sys.stderr)
+        sys.exit(2)
+    if args.hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)   # before the HIP runtime starts (torch import)
 
     import numpy as np
     import torch
@@ -647,7 +655,8 @@ def main():
     prof = ctx.profile_read(reset=True)
     ctx.profile(True, count_pairs=True)
     run_frames(ctx, model, cams, frames, masks, frame_window, cfg, K, Wu, out)
-    prof["pairs"] = ctx.profile_read(reset=True)["pairs"]
+    pp = ctx.profile_read(reset=True)
+    prof["pairs"], prof["blended"] = pp["pairs"], pp["blended"]
     ctx.profile(False)
     stages = {}
     for name in _lib.STAGES[:8]:
@@ -664,6 +673,10 @@ def main():
     pairs_per_frame = prof["pairs"] / K
     comp_tflops = pairs_per_frame * FLOPS_PER_PAIR / (comp["avg_ms"] * 1e-3) / 1e12
     comp["pairs_per_frame"] = int(pairs_per_frame)
+    # pairs that blended (alpha >= alpha_min while the pixel is live): the rest
+    # are evaluated because the pixel's wavefront cell is reached by the ellipse
+    comp["blended_pairs_per_frame"] = int(prof["blended"] / K)
+    comp["blended_fraction"] = round(prof["blended"] / max(prof["pairs"], 1), 4)
     comp["achieved_TFLOPs"] = round(comp_tflops, 3)
     comp["valu_frac_of_measured"] = round(pairs_per_frame * FLOPS_PER_PAIR / 2 / (comp["avg_ms"] * 1e-3)
                                           / peaks["valu_fma_lane_ops_per_s"], 4)
@@ -809,7 +822,8 @@ def main():
         "config": {"workload": "masked 4D Gaussian frame: 200k long-lifespan Gaussians (log s_t~N(-1,0.4)), "
                                "1352x1014, 20 cameras x 300 timestamps, keyframe masks every 10 frames "
                                "(temporal and tile predicate)",
-                   "autotuned": tuned, "streams": args.streams, "one_stream_fps": round(fps1, 2),
+                   "autotuned": tuned, "streams": args.streams,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")), "one_stream_fps": round(fps1, 2),
                    "default_config_fps": round(fps_default, 2),
                    "autotune_refinement_fps": {"/".join(str(x) for x in k): round(v, 1) for k, v in refine.items()},
                    "autotune_sweep_ms_per_frame": {

@@ -430,7 +430,7 @@ FDGS_API fdgs_status fdgs_check_overflow(fdgs_ctx *ctx, hipStream_t stream);
  * Per-stage timing with HIP events recorded on the caller's stream around each
  * kernel group of fdgs_render_forward / fdgs_render_backward, plus work
  * counters (processed and visible Gaussians, tile instances, and (pixel,
- * Gaussian) pairs evaluated by the compositor).  Profiling adds event records
+ * Gaussian) pairs evaluated by the compositor and, of those, blended).  Profiling adds event records
  * between kernels and a per-wavefront counter update in the compositor; it is
  * off by default.
  */
@@ -454,6 +454,7 @@ typedef struct {
     int64_t visible;
     int64_t instances;
     uint64_t pairs;                  /* (pixel, Gaussian) evaluations      */
+    uint64_t blended;                /* of those, pairs that were blended  */
 } fdgs_profile;
 
 /*

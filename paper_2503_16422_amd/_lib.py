@@ -85,7 +85,8 @@ class TuneResult(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 10), ("calls", ctypes.c_int64 * 10), ("processed", ctypes.c_int64),
-                ("visible", ctypes.c_int64), ("instances", ctypes.c_int64), ("pairs", ctypes.c_uint64)]
+                ("visible", ctypes.c_int64), ("instances", ctypes.c_int64), ("pairs", ctypes.c_uint64),
+                ("blended", ctypes.c_uint64)]
 
 
 class FdgsError(RuntimeError):

@@ -146,7 +146,7 @@ struct fdgs_ctx {
     int64_t *host_counts = nullptr;  // pinned
     // profiling
     int prof = 0;                  // 0 off, 1 stage events and counts, 2 also evaluated pairs
-    Buf prof_acc;                  // uint64[4]: processed, visible, instances, pairs
+    Buf prof_acc;                  // uint64[5]: processed, visible, instances, pairs, blended pairs
     std::vector<hipEvent_t> free_events;
     std::vector<PendingStage> pending;
     double ms[FDGS_NUM_STAGES] = {};
@@ -766,7 +766,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     float *T_out = need_state ? S->T_final.as<float>() : out_T;
     uint64_t *acc = nullptr;
     if (ctx->prof && !ctx->capturing) {
-        HIP_TRY(ensure(ctx->prof_acc, 4 * sizeof(uint64_t)));
+        HIP_TRY(ensure(ctx->prof_acc, 5 * sizeof(uint64_t)));
         acc = ctx->prof_acc.as<uint64_t>();
         HIP_TRY(launch_accumulate_counts(n_dev, n_total, counts, capacity, acc, stream));
     }
@@ -1148,8 +1148,8 @@ fdgs_status fdgs_profile_enable(fdgs_ctx *ctx, int32_t enable) {
     if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "fdgs_profile_enable: ctx is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     if (enable && !ctx->prof_acc.p) {
-        HIP_TRY(ensure(ctx->prof_acc, 4 * sizeof(uint64_t)));
-        HIP_TRY(hipMemset(ctx->prof_acc.p, 0, 4 * sizeof(uint64_t)));
+        HIP_TRY(ensure(ctx->prof_acc, 5 * sizeof(uint64_t)));
+        HIP_TRY(hipMemset(ctx->prof_acc.p, 0, 5 * sizeof(uint64_t)));
     }
     ctx->prof = enable <= 0 ? 0 : (enable >= 2 ? 2 : 1);
     return FDGS_OK;
@@ -1174,12 +1174,13 @@ fdgs_status fdgs_profile_read(fdgs_ctx *ctx, fdgs_profile *out, int32_t reset) {
         out->calls[k] = ctx->calls[k];
     }
     if (ctx->prof_acc.p) {
-        uint64_t acc[4];
+        uint64_t acc[5];
         HIP_TRY(hipMemcpy(acc, ctx->prof_acc.p, sizeof acc, hipMemcpyDeviceToHost));
         out->processed = (int64_t)acc[0];
         out->visible = (int64_t)acc[1];
         out->instances = (int64_t)acc[2];
         out->pairs = acc[3];
+        out->blended = acc[4];
         if (reset) HIP_TRY(hipMemset(ctx->prof_acc.p, 0, sizeof acc));
     }
     if (reset) {

@@ -126,7 +126,8 @@ hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, int64_t n, un
 hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, const int64_t *counts,
                                     int64_t capacity, uint64_t *acc, hipStream_t s);
 
-// Compositing.  pair_counter (optional) accumulates evaluated (pixel, Gaussian) pairs.
+// Compositing.  pair_counter (optional, two words) accumulates evaluated (pixel, Gaussian)
+// pairs and, of those, the pairs that were blended.
 // V views of W x H share one tile grid: item i renders tile i % n_tiles of
 // view i / n_tiles; view v writes out_rgb + v*3*W*H (out_T, n_contrib: + v*W*H).
 // sched == NULL: one workgroup per item in item order.  Otherwise sched holds

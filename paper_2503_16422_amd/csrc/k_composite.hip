@@ -35,7 +35,7 @@ struct CompArgs {
     float *out_rgb;
     float *out_T;
     uint32_t *n_contrib;
-    unsigned long long *pairs;   // optional counter of evaluated pairs
+    unsigned long long *pairs;   // optional counters: evaluated pairs, then blended pairs
     int32_t ppt;                 // pixels per thread (host-side dispatch only)
     int32_t V;                   // views sharing the launch
     const uint32_t *order;       // persistent schedule: (view, tile) items, longest list first
@@ -91,7 +91,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     // live, +inf once it has stopped (or lies outside the image), so a stopped
     // pixel fails every later test and its T stays the T at the stop.
     float fy[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], thr[PPT];
-    uint32_t last[PPT], stop[PPT];
+    uint32_t last[PPT], stop[PPT], blends[PPT];
     bool all_done = true;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -99,6 +99,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
         T[p] = 1.0f;
         C0[p] = C1[p] = C2[p] = 0.0f;
         last[p] = 0;
+        blends[p] = 0;
         // evaluated pairs (profiling): a single-pixel thread evaluates its list up
         // to its stop; a multi-pixel thread counts the records it evaluates live
         stop[p] = PPT == 1 ? end - start : 0u;
@@ -166,6 +167,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     C2[0] = fmaf(s_rec[3 * k + 2].x, w, C2[0]);
                     T[0] = test;
                     if constexpr (LAST) last[0] = pos;
+                    if constexpr (COUNT) ++blends[0];
                     if constexpr (MARK) {
                         // lanes here blended record k: the lowest one flags it
                         if (lane_id() == __builtin_ctzll(__ballot(1)))
@@ -214,7 +216,10 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                     C1[p] = fmaf(h.w, w, C1[p]);
                     C2[p] = fmaf(cb, w, C2[p]);
                     if constexpr (LAST) last[p] = ok ? pos : last[p];
-                    if constexpr (COUNT) stop[p] += (counted && thr[p] < kInf) ? 1u : 0u;
+                    if constexpr (COUNT) {
+                        stop[p] += (counted && thr[p] < kInf) ? 1u : 0u;
+                        blends[p] += ok ? 1u : 0u;
+                    }
                     T[p] = Tn;
                     thr[p] = hit != ok ? kInf : thr[p];   // alpha reached alpha_min, T would fall below thr
                     if constexpr (MARK) blended = blended || ok;
@@ -286,7 +291,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     }
     const int64_t plane = (int64_t)a.W * a.H;
     float *out_rgb = a.out_rgb + (int64_t)view * 3 * plane;
-    uint32_t evaluated = 0;
+    uint32_t evaluated = 0, blended = 0;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int py = py0 + p;
@@ -300,11 +305,16 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 if (a.n_contrib) a.n_contrib[view * plane + pix] = last[p];
             }
             evaluated += stop[p];
+            blended += blends[p];
         }
     }
     if constexpr (COUNT) {
         const unsigned long long w = wave_sum((unsigned long long)evaluated);
-        if (lane_id() == 0) atomicAdd(a.pairs, w);
+        const unsigned long long b = wave_sum((unsigned long long)blended);
+        if (lane_id() == 0) {
+            atomicAdd(a.pairs, w);
+            atomicAdd(a.pairs + 1, b);
+        }
     }
 }
 

@@ -353,7 +353,8 @@ class Context:
         _lib.check(self.lib.fdgs_profile_read(self.handle, ctypes.byref(p), 1 if reset else 0))
         return {"ms": {name: p.ms[k] for k, name in enumerate(_lib.STAGES)},
                 "calls": {name: p.calls[k] for k, name in enumerate(_lib.STAGES)},
-                "processed": p.processed, "visible": p.visible, "instances": p.instances, "pairs": p.pairs}
+                "processed": p.processed, "visible": p.visible, "instances": p.instances, "pairs": p.pairs,
+                "blended": p.blended}
 
 
 def _own_stream(ctx: Context) -> "torch.cuda.Stream":
