@@ -45,9 +45,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, bool valid
 // Per-block digit histogram, stored digit-major: hist[d * nb + b].  Block b
 // owns keys [b * KPT * kNT, (b + 1) * KPT * kNT).  All loads are issued
 // before the first use (indices clamped to the last counted key, so no branch
-// separates them), and each wave adds one count per distinct digit of a
-// round: skewed digits (the exponent byte of depths, the high bits of tile
-// ids) do not serialise on one LDS address.
+// separates them).  Counting is by LDS atomics: a round of 64 keys whose
+// digits are all equal (common for skewed digits: the exponent byte of
+// depths, the high bits of tile ids) adds its count with one atomic, any other
+// round one atomic per key (distinct digits proceed in parallel, equal ones
+// serialise only among themselves).
 template <int KPT>
 __global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, const int64_t *n_dev,
                                                       int64_t n_max, int shift, int bits, uint32_t *hist) {
@@ -66,14 +68,19 @@ __global__ void __launch_bounds__(kNT) upsweep_kernel(const uint32_t *keys, cons
         for (int r = 0; r < KPT; ++r) k[r] = 0u;
     }
     __syncthreads();
-    const uint64_t lt_mask = (lane_id() == 0) ? 0ull : ((~0ull) >> (64 - lane_id()));
 #pragma unroll
     for (int r = 0; r < KPT; ++r) {
+        // the valid lanes of a round are a prefix of the wave (lane 0 first)
         const bool valid = base + (int64_t)r * 64 < n;
         const uint32_t d = (k[r] >> shift) & mask;
-        const uint64_t match = match_digit(d, bits, valid);
-        const uint32_t cnt = __popcll(match);
-        if (valid && __popcll(match & lt_mask) == cnt - 1) atomicAdd(&h[d], cnt);   // last lane of its group
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        const uint64_t vm = __ballot(valid);
+        const uint64_t same = __ballot(valid && d == d0);
+        if (same == vm) {
+            if (lane_id() == 0 && vm != 0ull) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[d], 1u);
+        }
     }
     __syncthreads();
     if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * gridDim.x + c] = h[threadIdx.x];   // rows of used digits
@@ -95,6 +102,66 @@ __global__ void __launch_bounds__(1024) rowscan_kernel(uint32_t *hist, int64_t n
         carry += tot;
     }
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+// The same scan for long rows (more than kRowLongAbove blocks, such as the
+// tile sort of an unfiltered frame).  A round covers up to kRowIpt counts per
+// thread: the counts are loaded coalesced into LDS, each thread scans its
+// kRowIpt consecutive ones (LDS rows padded by one word in 32, so that the
+// strided reads hit distinct banks), and the results leave through LDS as
+// coalesced stores; rows of up to 16384 blocks take one round (the scan above walks them
+// in 1024-count rounds, one global latency each).  Short rows stay with the
+// scan above: with frames pipelined over streams, this kernel's extra
+// barriers cost more than its rounds save (measured 8589 against 7891
+// headline frames/s on four streams).  The LDS is sized to the counts a round
+// takes (row_scan_lds_bytes).
+constexpr int kRowIpt = 16;
+constexpr int64_t kRowLongAbove = 4096;
+__device__ __forceinline__ int row_pad(int j) { return j + (j >> 5); }
+inline int row_scan_per(int64_t nb) { return (int)std::min<int64_t>(kRowIpt, (nb + 1023) / 1024); }
+inline size_t row_scan_lds_bytes(int64_t nb) {
+    const int span = 1024 * std::max(row_scan_per(nb), 1);
+    return sizeof(uint32_t) * (size_t)(span + span / 32);
+}
+__global__ void __launch_bounds__(1024) rowscan_long_kernel(uint32_t *hist, int64_t nb,
+                                                       uint32_t *digit_total) {
+    __shared__ uint32_t tmp[1024 / 64 + 1];
+    extern __shared__ uint32_t s_v[];   // row_scan_lds_bytes(nb)
+    uint32_t *row = hist + (int64_t)blockIdx.x * nb;
+    const int per = (int)min((int64_t)kRowIpt, (nb + 1023) / 1024);   // counts per thread and round (>= 1)
+    const int t = (int)threadIdx.x;
+    uint32_t carry = 0;
+    for (int64_t start = 0; start < nb; start += 1024 * per) {
+#pragma unroll
+        for (int i = 0; i < kRowIpt; ++i) {
+            const int j = i * 1024 + t;
+            if (i < per) s_v[row_pad(j)] = start + j < nb ? row[start + j] : 0u;
+        }
+        __syncthreads();
+        uint32_t v[kRowIpt];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kRowIpt; ++i) {
+            v[i] = i < per ? s_v[row_pad(t * per + i)] : 0u;
+            sum += v[i];
+        }
+        uint32_t tot;
+        uint32_t ex = carry + block_exclusive_sum<1024>(sum, tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kRowIpt; ++i) {
+            if (i < per) s_v[row_pad(t * per + i)] = ex;
+            ex += v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kRowIpt; ++i) {
+            const int j = i * 1024 + t;
+            if (i < per && start + j < nb) row[start + j] = s_v[row_pad(j)];
+        }
+        __syncthreads();
+        carry += tot;
+    }
+    if (t == 0) digit_total[blockIdx.x] = carry;
 }
 
 // Stable scatter of one block's KPT * kNT keys.  Wave w owns the contiguous
@@ -482,7 +549,11 @@ static void sort_pass(const uint32_t *src_k, const uint32_t *src_v, uint32_t *ds
                            bits, hist);
         hist_cols = nb;
     }
-    hipLaunchKernelGGL(rowscan_kernel, dim3(1u << bits), dim3(1024), 0, s, hist, hist_cols, digit_total);
+    if (hist_cols > kRowLongAbove)
+        hipLaunchKernelGGL(rowscan_long_kernel, dim3(1u << bits), dim3(1024), row_scan_lds_bytes(hist_cols), s, hist,
+                           hist_cols, digit_total);
+    else
+        hipLaunchKernelGGL(rowscan_kernel, dim3(1u << bits), dim3(1024), 0, s, hist, hist_cols, digit_total);
     hipLaunchKernelGGL((downsweep_kernel<KPT>), dim3((unsigned)nb), dim3(kNT), 0, s, src_k, src_v, dst_k, dst_v,
                        n_dev, n_max, shift, bits, (const uint32_t *)hist, hist_cols, (int)(hist_cols / nb),
                        (const uint32_t *)digit_total);

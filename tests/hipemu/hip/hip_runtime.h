@@ -99,6 +99,8 @@ inline uint64_t __ballot(int pred) {
     return m;
 }
 inline int __popcll(uint64_t x) { return __builtin_popcountll(x); }
+// the kernels that read the first lane do so with every lane of the wave active
+#define __builtin_amdgcn_readfirstlane(v) wave_exchange((v), 0)
 inline int __popc(uint32_t x) { return __builtin_popcount(x); }
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }

@@ -139,5 +139,28 @@ int main(int argc, char **argv) {
         std::printf("trial %d: %lld instances, capacity %lld, histogram columns %lld: ok\n", trial, (long long)n_inst,
                     (long long)capacity, (long long)hist_cols);
     }
+    // the digit-row scan on rows longer than one round (several counts per
+    // thread and round, and a ragged last round): 3 rows of 40001 blocks
+    {
+        const int64_t nb = 40001;
+        std::vector<uint32_t> hist(3 * nb), want(3 * nb), tot(3);
+        for (auto &v : hist) v = (uint32_t)(rng() % 1000);
+        for (int d = 0; d < 3; ++d) {
+            uint32_t run = 0;
+            for (int64_t j = 0; j < nb; ++j) {
+                want[d * nb + j] = run;
+                run += hist[d * nb + j];
+            }
+            want.push_back(run);
+        }
+        hipLaunchKernelGGL(rowscan_long_kernel, dim3(3), dim3(1024), row_scan_lds_bytes(nb), nullptr, hist.data(), nb,
+                           tot.data());
+        for (int d = 0; d < 3; ++d) {
+            for (int64_t j = 0; j < nb; ++j)
+                if (hist[d * nb + j] != want[d * nb + j]) return fail("row scan");
+            if (tot[d] != want[3 * nb + d]) return fail("row scan total");
+        }
+        std::printf("row scan of 3 x %lld counts: ok\n", (long long)nb);
+    }
     return 0;
 }
