@@ -47,19 +47,67 @@ struct Buf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// Blocks replaced by a larger one.  Kernels enqueued before the growth (on
+// whatever stream the caller gave) may still read the old block, so it is not
+// freed at once: it waits here until a device-wide synchronisation that
+// starts after its retirement -- fdgs_destroy, or a growth that finds more
+// than kRetiredLimit bytes waiting -- so that a growth does not stall every
+// stream of the process.  Growth is geometric (1.5x), so a buffer retires a
+// few blocks at most.
+std::mutex g_retired_mu;
+std::vector<std::pair<int, void *>> g_retired;   // (device, block)
+size_t g_retired_bytes = 0;
+constexpr size_t kRetiredLimit = size_t(1) << 30;
+
+hipError_t free_retired() {
+    std::vector<std::pair<int, void *>> mine;
+    {
+        std::lock_guard<std::mutex> lk(g_retired_mu);
+        mine.swap(g_retired);
+        g_retired_bytes = 0;
+    }
+    if (mine.empty()) return hipSuccess;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    // every block taken here was retired before this synchronisation started
+    std::vector<int> devs;
+    for (const auto &r : mine)
+        if (std::find(devs.begin(), devs.end(), r.first) == devs.end()) devs.push_back(r.first);
+    for (int d : devs) {
+        const hipError_t f = hipSetDevice(d) == hipSuccess ? hipDeviceSynchronize() : hipErrorInvalidDevice;
+        if (e == hipSuccess) e = f;
+    }
+    for (const auto &r : mine) {
+        (void)hipSetDevice(r.first);
+        const hipError_t f = hipFree(r.second);
+        if (e == hipSuccess) e = f;
+    }
+    (void)hipSetDevice(cur);
+    return e;
+}
+
 hipError_t ensure(Buf &b, size_t bytes) {
     bytes = std::max<size_t>(bytes, 256);
     if (bytes <= b.cap) return hipSuccess;
+    const size_t want = std::max(bytes, b.cap + b.cap / 2);
     if (b.p) {
-        // kernels already enqueued may still use the old block
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return e;
-        e = hipFree(b.p);
-        if (e != hipSuccess) return e;
+        bool flush = false;
+        int dev = 0;
+        const hipError_t de = hipGetDevice(&dev);
+        if (de != hipSuccess) return de;
+        {
+            std::lock_guard<std::mutex> lk(g_retired_mu);
+            g_retired.emplace_back(dev, b.p);
+            g_retired_bytes += b.cap;
+            flush = g_retired_bytes > kRetiredLimit;
+        }
         b.p = nullptr;
         b.cap = 0;
+        if (flush) {
+            const hipError_t e = free_retired();
+            if (e != hipSuccess) return e;
+        }
     }
-    const size_t want = std::max(bytes, b.cap + b.cap / 2);
     hipError_t e = hipMalloc(&b.p, want);
     if (e != hipSuccess) {
         b.p = nullptr;
@@ -247,6 +295,7 @@ fdgs_status fdgs_destroy(fdgs_ctx *ctx) {
     if (!ctx) return FDGS_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    (void)free_retired();
     for (fdgs_state *s : ctx->states) {
         s->free_all();
         delete s;
