@@ -61,9 +61,11 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     constexpr int NT = TW * TH / PPT;
     static_assert(NT % 64 == 0, "whole wavefronts per tile");
     using C = Cells<TW, TH, PPT>;
-    // per-wavefront bitmaps of the batch's records that reach its cell (several
-    // pixels per thread; a single-pixel thread branches per pixel instead)
-    constexpr bool kBits = C::NW > 1 && PPT > 1;
+    // per-wavefront bitmaps of the batch's records that reach its cell (with
+    // several cells per tile; a single wavefront per tile walks every record,
+    // branching per pixel)
+    constexpr bool kBits = C::NW > 1;
+    constexpr bool kBranchy = PPT == 1 && !kBits;
     const bool cull = a.rp.tile_cull != 0;   // without tile culling every record reaches every cell
     constexpr int kWords = BATCH / 64;
     __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
@@ -100,15 +102,15 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
         C0[p] = C1[p] = C2[p] = 0.0f;
         last[p] = 0;
         blends[p] = 0;
-        // evaluated pairs (profiling): a single-pixel thread evaluates its list up
-        // to its stop; a multi-pixel thread counts the records it evaluates live
-        stop[p] = PPT == 1 ? end - start : 0u;
+        // evaluated pairs (profiling): the branchy walk evaluates its list up to
+        // its stop; the select-based walk counts the records it evaluates live
+        stop[p] = kBranchy ? end - start : 0u;
         const bool inside = px < a.W && py0 + p < a.H;
         thr[p] = inside ? tmin : kInf;
         all_done = all_done && !inside;
     }
     for (uint32_t base = start; base < end; base += BATCH) {
-        if constexpr (PPT > 1) {
+        if constexpr (!kBranchy) {
             bool left = false;
 #pragma unroll
             for (int p = 0; p < PPT; ++p) left = left || thr[p] < kInf;
@@ -143,7 +145,7 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
             }
         }
         __syncthreads();
-        if constexpr (PPT == 1) {
+        if constexpr (kBranchy) {
             if (!all_done) {
                 for (int k = 0; k < cnt; ++k) {
                     const float4 g = s_rec[3 * k];
@@ -177,8 +179,9 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
                 }
             }
         } else if (__ballot(!all_done) != 0ull) {
-            // several pixels: select-based updates, no branches or lane masks per
-            // pixel, and control flow uniform over the wavefront (lanes whose pixels
+            // select-based updates (several pixels per thread, or one pixel and
+            // several cells per tile): no branches or lane masks per pixel, and
+            // control flow uniform over the wavefront (lanes whose pixels
             // stopped run along with w = 0), so the wavefront sums see every lane
             // alpha of record k at the thread's pixels (clamped to the float with bit
             // pattern cap: alpha_max, or 0 to make the record a no-op)
