@@ -272,6 +272,28 @@ FDGS_API fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state,
                                  const float *dL_drgb, const fdgs_grads *grads,
                                  hipStream_t stream);
 
+/*
+ * The two phases of fdgs_render_backward, for callers that order them apart
+ * (adjoint of Eq. 2-3, then of Sec. 3's slicing and projection):
+ *   - fdgs_render_backward_2d: the adjoint of the blend, back to front, into
+ *     the state's own per-Gaussian gradients of the 2D centre, conic, opacity
+ *     and colour.  It writes nothing outside the state.
+ *   - fdgs_render_backward_params: those gradients through the projection,
+ *     Eq. 1's slicing and the activations, ACCUMULATED (+=) into `grads` (as in
+ *     fdgs_render_backward: per Gaussian a plain read-modify-write, so two
+ *     calls that add into the same buffers must be ordered, e.g. by events).
+ *     FDGS_ERR_STATE unless fdgs_render_backward_2d ran on the state since its
+ *     last forward.
+ * fdgs_render_backward_2d then fdgs_render_backward_params on one stream is
+ * fdgs_render_backward.  A multi-view step can overlap the first phases of
+ * several views (one context each, on their own streams) and chain only the
+ * second.
+ */
+FDGS_API fdgs_status fdgs_render_backward_2d(fdgs_ctx *ctx, fdgs_state *state, const float *dL_drgb,
+                                             hipStream_t stream);
+FDGS_API fdgs_status fdgs_render_backward_params(fdgs_ctx *ctx, fdgs_state *state, const fdgs_grads *grads,
+                                                 hipStream_t stream);
+
 /* Release a state (NULL is accepted). */
 FDGS_API fdgs_status fdgs_state_release(fdgs_ctx *ctx, fdgs_state *state);
 

@@ -24,6 +24,7 @@ MASK_CONTRIBUTED = 2
 
 EXPORTS = ["fdgs_last_error", "fdgs_version", "fdgs_create", "fdgs_destroy", "fdgs_render_cfg_default",
            "fdgs_slice_4d", "fdgs_build_active_mask", "fdgs_build_active_mask_noalloc", "fdgs_mask_overlap", "fdgs_measure_peaks", "fdgs_render_forward", "fdgs_render_backward",
+           "fdgs_render_backward_2d", "fdgs_render_backward_params",
            "fdgs_state_release", "fdgs_state_binning", "fdgs_check_overflow", "fdgs_profile_enable",
            "fdgs_profile_read", "fdgs_render_batch", "fdgs_autotune", "fdgs_spatial_score",
            "fdgs_variation_score", "fdgs_prune", "fdgs_adam_step", "fdgs_sh_kmeans"]
@@ -120,6 +121,8 @@ def load() -> ctypes.CDLL:
     lib.fdgs_measure_peaks.argtypes = [VP, P(D), VP]
     lib.fdgs_render_forward.argtypes = [VP, P(Model), VP, VP, P(Camera), D, P(RenderCfg), VP, VP, P(VP), VP]
     lib.fdgs_render_backward.argtypes = [VP, VP, VP, P(Grads), VP]
+    lib.fdgs_render_backward_2d.argtypes = [VP, VP, VP, VP]
+    lib.fdgs_render_backward_params.argtypes = [VP, VP, P(Grads), VP]
     lib.fdgs_state_release.argtypes = [VP, VP]
     lib.fdgs_state_binning.argtypes = [VP, VP, P(Binning), VP]
     lib.fdgs_check_overflow.argtypes = [VP, VP]

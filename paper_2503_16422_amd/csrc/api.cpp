@@ -141,6 +141,7 @@ int bits_for(int64_t v) {   // bits needed to represent values in [0, v)
 struct fdgs_state {
     fdgs_ctx *owner = nullptr;
     bool has_forward = false;
+    bool has_g2d = false;   // a backward's first phase ran since the last forward
     // per processed Gaussian
     Buf rec, depth_key, rect, tiles, visible, vis_pos, order_k, order_v, order_k2, order_v2, offsets, view_of;
     Buf bucket;        // depth buckets: counts, cursors, starts, key range
@@ -887,6 +888,7 @@ fdgs_status fdgs_render_forward(fdgs_ctx *ctx, const fdgs_model *model, const ui
     S->t = t;
     S->n_max = model->n;
     S->has_forward = true;
+    S->has_g2d = false;
     return FDGS_OK;
 }
 
@@ -1122,37 +1124,85 @@ fdgs_status fdgs_autotune(fdgs_ctx *ctx, const fdgs_model *scenes, int32_t n_sce
     return FDGS_OK;
 }
 
-fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *dL_drgb, const fdgs_grads *grads,
-                                 hipStream_t stream) {
-    const char *fn = "fdgs_render_backward";
+}  // extern "C"
+
+namespace {
+
+// The state a backward phase may use, or an error.
+fdgs_status backward_state(fdgs_ctx *ctx, fdgs_state *state, const char *fn, fdgs_state **out) {
     if (!ctx) return fail(FDGS_ERR_INVALID_ARG, "%s: ctx is NULL", fn);
     fdgs_state *S = state ? find_state(ctx, state) : nullptr;
     if (!S) return fail(FDGS_ERR_STATE, "%s: state is not a live state of this context", fn);
     if (!S->has_forward) return fail(FDGS_ERR_STATE, "%s: state holds no forward pass", fn);
-    if (!dL_drgb || !grads) return fail(FDGS_ERR_INVALID_ARG, "%s: dL_drgb or grads is NULL", fn);
     if (S->model.sh_index)
         return fail(FDGS_ERR_UNSUPPORTED, "%s: the forward used vector-quantised SH (no adjoint)", fn);
+    *out = S;
+    return FDGS_OK;
+}
+
+fdgs_status check_grads(const fdgs_state *S, const fdgs_grads *grads, const char *fn) {
+    if (!grads) return fail(FDGS_ERR_INVALID_ARG, "%s: grads is NULL", fn);
     if (S->model.n > 0 && (!grads->mean || !grads->log_scale || !grads->q_left || !grads->q_right ||
                            !grads->opacity_logit || !grads->sh))
         return fail(FDGS_ERR_INVALID_ARG, "%s: a gradient pointer is NULL", fn);
+    return FDGS_OK;
+}
+
+// Phase 1: adjoint compositor into the state's per-Gaussian 2D gradients.
+fdgs_status enqueue_backward_2d(fdgs_ctx *ctx, fdgs_state *S, const float *dL_drgb, hipStream_t stream) {
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(ensure(S->g2d, sizeof(float) * 9 * std::max<int64_t>(S->n_max, 1)));
-    {
-        StageTimer tm(ctx, FDGS_STAGE_BWD_COMPOSITE, stream);
-        HIP_TRY(launch_fill_u32(S->g2d.as<uint32_t>(), 9 * std::max<int64_t>(S->n_max, 1), 0u, stream));
-        HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ppt, S->ranges.as<uint32_t>(),
-                                          S->sorted_ids, S->rec.as<Rec2D>(), S->T_final.as<float>(),
-                                          S->n_contrib.as<uint32_t>(), dL_drgb, S->g2d.as<float>(), S->n_max,
-                                          stream));
-    }
-    {
-        StageTimer tm(ctx, FDGS_STAGE_BWD_PREPROCESS, stream);
-        const int64_t *n_proc_dev = S->idx ? S->n_idx_dev : nullptr;
-        HIP_TRY(launch_preprocess_backward(kmodel(&S->model), S->idx, n_proc_dev, S->n_max, S->cam, S->t, S->rp,
-                                           S->vis_list, S->counts.as<int64_t>(), S->g2d.as<float>(), *grads,
-                                           stream));
-    }
+    StageTimer tm(ctx, FDGS_STAGE_BWD_COMPOSITE, stream);
+    HIP_TRY(launch_fill_u32(S->g2d.as<uint32_t>(), 9 * std::max<int64_t>(S->n_max, 1), 0u, stream));
+    HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ppt, S->ranges.as<uint32_t>(), S->sorted_ids,
+                                      S->rec.as<Rec2D>(), S->T_final.as<float>(), S->n_contrib.as<uint32_t>(),
+                                      dL_drgb, S->g2d.as<float>(), S->n_max, stream));
+    S->has_g2d = true;
     return FDGS_OK;
+}
+
+// Phase 2: the 2D gradients through projection, slicing and activations into grads.
+fdgs_status enqueue_backward_params(fdgs_ctx *ctx, fdgs_state *S, const fdgs_grads *grads, hipStream_t stream) {
+    HIP_TRY(hipSetDevice(ctx->device));
+    StageTimer tm(ctx, FDGS_STAGE_BWD_PREPROCESS, stream);
+    const int64_t *n_proc_dev = S->idx ? S->n_idx_dev : nullptr;
+    HIP_TRY(launch_preprocess_backward(kmodel(&S->model), S->idx, n_proc_dev, S->n_max, S->cam, S->t, S->rp,
+                                       S->vis_list, S->counts.as<int64_t>(), S->g2d.as<float>(), *grads, stream));
+    return FDGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdgs_status fdgs_render_backward(fdgs_ctx *ctx, fdgs_state *state, const float *dL_drgb, const fdgs_grads *grads,
+                                 hipStream_t stream) {
+    const char *fn = "fdgs_render_backward";
+    fdgs_state *S = nullptr;
+    if (fdgs_status st = backward_state(ctx, state, fn, &S)) return st;
+    if (!dL_drgb) return fail(FDGS_ERR_INVALID_ARG, "%s: dL_drgb is NULL", fn);
+    if (fdgs_status st = check_grads(S, grads, fn)) return st;
+    if (fdgs_status st = enqueue_backward_2d(ctx, S, dL_drgb, stream)) return st;
+    return enqueue_backward_params(ctx, S, grads, stream);
+}
+
+fdgs_status fdgs_render_backward_2d(fdgs_ctx *ctx, fdgs_state *state, const float *dL_drgb, hipStream_t stream) {
+    const char *fn = "fdgs_render_backward_2d";
+    fdgs_state *S = nullptr;
+    if (fdgs_status st = backward_state(ctx, state, fn, &S)) return st;
+    if (!dL_drgb) return fail(FDGS_ERR_INVALID_ARG, "%s: dL_drgb is NULL", fn);
+    return enqueue_backward_2d(ctx, S, dL_drgb, stream);
+}
+
+fdgs_status fdgs_render_backward_params(fdgs_ctx *ctx, fdgs_state *state, const fdgs_grads *grads,
+                                        hipStream_t stream) {
+    const char *fn = "fdgs_render_backward_params";
+    fdgs_state *S = nullptr;
+    if (fdgs_status st = backward_state(ctx, state, fn, &S)) return st;
+    if (!S->has_g2d)
+        return fail(FDGS_ERR_STATE, "%s: no fdgs_render_backward_2d since the state's last forward", fn);
+    if (fdgs_status st = check_grads(S, grads, fn)) return st;
+    return enqueue_backward_params(ctx, S, grads, stream);
 }
 
 fdgs_status fdgs_state_release(fdgs_ctx *ctx, fdgs_state *state) {

@@ -220,6 +220,22 @@ class Context:
                                                  _stream(self.device)))
         return grads
 
+    def backward_2d(self, state: State, dL_drgb: torch.Tensor):
+        """First phase of the adjoint (the blend), into the state's own 2D gradients."""
+        dL = dL_drgb.contiguous()
+        _lib.check(self.lib.fdgs_render_backward_2d(self.handle, state.handle, _ptr(dL), _stream(self.device)))
+
+    def backward_params(self, state: State, model: GaussianModel, grads=None):
+        """Second phase: the state's 2D gradients added into the model's gradients."""
+        if grads is None:
+            grads = {k: torch.zeros_like(getattr(model, k)) for k in GaussianModel.FIELDS}
+        g = _lib.Grads()
+        for k in GaussianModel.FIELDS:
+            setattr(g, k, grads[k].data_ptr())
+        _lib.check(self.lib.fdgs_render_backward_params(self.handle, state.handle, ctypes.byref(g),
+                                                        _stream(self.device)))
+        return grads
+
     def release(self, state: State):
         _lib.check(self.lib.fdgs_state_release(self.handle, state.handle))
         state.handle = ctypes.c_void_p()
@@ -374,10 +390,11 @@ def forward_backward_views(ctxs, model: GaussianModel, views, cfg: Optional[_lib
     views: (cam, t, idx, n_idx) per view (idx, n_idx may be None: dense).
     loss_grad(v, rgb) returns dL_v/drgb for view v's image.  View v is rendered
     and differentiated by ctxs[v % len(ctxs)] on a stream of that context's
-    own, so a view's forward (short launches that fill the device poorly)
-    runs beside the previous view's adjoint.  The adjoints are chained in view
-    order by events, so the gradients are added in the same order, and come out
-    the same, as in a loop over the views on one stream.  states: States to
+    own, so a view's forward (short launches that fill the device poorly) and
+    the blend adjoint (into the view's own state) run beside other views'
+    work.  Only the adjoints' second phase, which adds into `grads`, is chained
+    in view order by events, so the gradients are added in the same order as
+    in a loop over the views on one stream.  states: States to
     reuse (one per view, each owned by the context that renders its view) or
     None; the list of states is returned.  The work starts after everything
     queued on the caller's current stream, and that stream waits for the last
@@ -401,10 +418,10 @@ def forward_backward_views(ctxs, model: GaussianModel, views, cfg: Optional[_lib
         with torch.cuda.stream(s):
             rgb, _, st = c.render(model, cam, t, cfg, idx=idx, n_idx=n_idx, keep_state=st if st is not None else True)
             states[v] = st
-            dL = loss_grad(v, rgb)
+            c.backward_2d(st, loss_grad(v, rgb))
             if prev is not None:
                 s.wait_event(prev)
-            c.backward(st, dL, model, grads)
+            c.backward_params(st, model, grads)
             prev = torch.cuda.Event()
             prev.record(s)
     if prev is not None:

@@ -50,6 +50,8 @@ def test_null_context_rejected_without_gpu(lib):
                                  ctypes.byref(cfg), None, None, None, None)
     assert st == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_render_backward(None, None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_render_backward_2d(None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
+    assert lib.fdgs_render_backward_params(None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_build_active_mask(None, None, None, None, None, None, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_state_release(None, None) == _lib.FDGS_ERR_INVALID_ARG
     assert lib.fdgs_check_overflow(None, None) == _lib.FDGS_ERR_INVALID_ARG

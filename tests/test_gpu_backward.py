@@ -185,3 +185,27 @@ def test_views_pipelined_over_contexts_match_one_stream(ctx):
             c.close()
         for k in NAMES:
             assert torch.allclose(got[k], ref[k], rtol=1e-5, atol=1e-6 * float(ref[k].abs().max()) + 1e-12), (n_ctx, k)
+
+
+def test_backward_in_two_phases(ctx):
+    """fdgs_render_backward_2d then fdgs_render_backward_params adds the same
+    gradients as fdgs_render_backward (up to the order of float atomics); the
+    second phase is refused on a state whose first phase has not run since its
+    forward."""
+    from paper_2503_16422_amd.render import GaussianModel
+    sc = scene_small(1500, seed=13, grow=0.5)
+    cam = inputs.look_at_camera(25.0, 3.0, 96, 80)
+    model = GaussianModel.from_scene(sc, "cuda:0")
+    rgb, _, state = ctx.render(model, cam, 0.55, keep_state=True)
+    G = torch.from_numpy(np.random.default_rng(5).standard_normal((3, 80, 96)).astype(np.float32)).cuda()
+    ref = ctx.backward(state, G, model)
+    rgb, _, state = ctx.render(model, cam, 0.55, keep_state=state)
+    with pytest.raises(_lib.FdgsError) as e:
+        ctx.backward_params(state, model)
+    assert e.value.code == _lib.FDGS_ERR_STATE
+    ctx.backward_2d(state, G)
+    got = ctx.backward_params(state, model)
+    torch.cuda.synchronize()
+    ctx.release(state)
+    for k in NAMES:
+        assert torch.allclose(got[k], ref[k], rtol=1e-5, atol=1e-6 * float(ref[k].abs().max()) + 1e-12), k
