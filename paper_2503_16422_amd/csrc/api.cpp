@@ -788,8 +788,8 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     // the duplicate writes the tile sort's first-digit histogram when its windows tile the sort's blocks
     const int tile_bits = std::max(1, bits_for(n_keys));
     const int sort_chunk = radix_chunk(capacity);
-    const int64_t hist_cols = (capacity > 0 && sort_chunk % duplicate_window() == 0)
-                                  ? (capacity + sort_chunk - 1) / sort_chunk * (sort_chunk / duplicate_window())
+    const int64_t hist_cols = (capacity > 0 && sort_chunk % duplicate_window(capacity) == 0)
+                                  ? (capacity + sort_chunk - 1) / sort_chunk * (sort_chunk / duplicate_window(capacity))
                                   : 0;
     HIP_TRY(ensure(S->scratch, std::max(scratch, sort_scratch_bytes(capacity, hist_cols))));
     {

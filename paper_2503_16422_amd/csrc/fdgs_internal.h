@@ -104,9 +104,9 @@ hipError_t launch_scatter_visible(const uint8_t *visible, const uint32_t *pos,
 hipError_t launch_fix_depth_ties(uint32_t *keys32, uint32_t *vals, const uint64_t *depth_key,
                                  const int64_t *n_vis_dev, int64_t n_max, int32_t *flag, hipStream_t s);
 // Tile key = view * tiles_per_view + ty * tiles_x + tx (view_of null: view 0).  Instances are written
-// in windows of duplicate_window(); with hist, window w also writes hist[d * hist_cols + w] = its count
+// in windows of duplicate_window(capacity); with hist, window w also writes hist[d * hist_cols + w] = its count
 // of keys whose low hist_bits bits equal d (d < 256), and the launch has exactly hist_cols windows.
-int duplicate_window();
+int duplicate_window(int64_t capacity);
 hipError_t launch_duplicate(const uint32_t *order, const uint64_t *offsets, const int32_t *rect,
                             const Rec2D *rec, const uint32_t *view_of, const int64_t *n_vis_dev, int64_t n_max,
                             const RenderParams &rp, uint32_t *tile_keys, uint32_t *ids,

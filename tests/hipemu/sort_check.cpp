@@ -84,8 +84,8 @@ int main(int argc, char **argv) {
         int bits = 1;
         while ((1 << bits) < n_tiles) ++bits;
         const int chunk = radix_chunk(capacity);
-        const int64_t hist_cols = chunk % duplicate_window() == 0
-                                      ? (capacity + chunk - 1) / chunk * (chunk / duplicate_window()) : 0;
+        const int64_t hist_cols = chunk % duplicate_window(capacity) == 0
+                                      ? (capacity + chunk - 1) / chunk * (chunk / duplicate_window(capacity)) : 0;
         std::vector<uint8_t> scratch(sort_scratch_bytes(capacity, hist_cols));
         std::vector<uint32_t> keys(capacity, 0xdeadu), ids(capacity, 0xdeadu), keys2(capacity), ids2(capacity);
         int64_t n_vis_dev = n_vis, n_inst_dev = n_inst;
@@ -100,7 +100,7 @@ int main(int argc, char **argv) {
         if (hist_cols) {
             const uint32_t *h = reinterpret_cast<const uint32_t *>(scratch.data());
             const int fb = radix_first_bits(0, bits);
-            const int E = duplicate_window();
+            const int E = duplicate_window(capacity);
             std::vector<uint32_t> c(256 * hist_cols, 0);
             for (int64_t i = 0; i < n_inst; ++i) ++c[(keys[i] & ((1u << fb) - 1u)) * hist_cols + i / E];
             for (int64_t x = 0; x < 256 * hist_cols; ++x)
