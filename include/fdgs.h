@@ -221,7 +221,7 @@ FDGS_API fdgs_status fdgs_mask_overlap(const uint32_t *bits_a, const uint32_t *b
  * at most FDGS_NOALLOC_MAX_GAUSSIANS, else FDGS_ERR_INVALID_ARG.  Outputs and
  * limits on the spec as for fdgs_build_active_mask, which gives bit-identical
  * results.  Its scratch (the window's frame times, the mask cameras and the
- * compaction's per-chunk counts) is a static device array of 1 MiB on each
+ * compaction's per-chunk counts) is a static device array of 2 MiB on each
  * GPU the library runs on, held until the process ends and shared by every
  * call on that GPU: calls that overlap on one GPU (on different streams or
  * host threads) race.  Runs on the current HIP device; synchronises `stream`.

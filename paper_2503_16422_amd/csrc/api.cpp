@@ -584,11 +584,12 @@ namespace {
 // hipGetSymbolAddress returns for the current device.
 //   [0, 2 KiB)        frame times (double[256])
 //   [2 KiB, 12 KiB)   mask cameras (KCam[64], 144 B each)
-//   [12 KiB, 1 MiB)   per-chunk counts of the compaction (compact_scratch_bytes(n))
+//   [12 KiB, 2 MiB)   per-chunk counts of the compaction (compact_scratch_bytes(n): 8 B per
+//                     1024 Gaussians, 1 MiB at the maximum of 2^27)
 constexpr size_t kNoAllocFrames = 0;
 constexpr size_t kNoAllocViews = 2048;
 constexpr size_t kNoAllocCompact = 12288;
-constexpr size_t kNoAllocBytes = size_t(1) << 20;
+constexpr size_t kNoAllocBytes = size_t(2) << 20;
 static_assert(sizeof(double) * kMaskMaxFrames <= kNoAllocViews - kNoAllocFrames, "frame times fit");
 static_assert(sizeof(KCam) * kMaskMaxViews <= kNoAllocCompact - kNoAllocViews, "mask cameras fit");
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];

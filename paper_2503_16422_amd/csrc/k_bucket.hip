@@ -30,7 +30,7 @@ namespace fdgs {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kKeysPerThread = 8;
+constexpr int kKeysPerThread = 4;   // 1024 keys per counting / scattering workgroup
 constexpr int kChunk = kNT * kKeysPerThread;
 constexpr int kSortNT = 256;
 constexpr int kCap = 2048;                 // positions a block sorts in LDS at once

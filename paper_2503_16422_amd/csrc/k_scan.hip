@@ -9,7 +9,8 @@ namespace fdgs {
 namespace {
 
 constexpr int kNT = 256;         // threads per block
-constexpr int kItems = 8;        // items per thread
+constexpr int kItems = 4;        // items per thread: 1024-item chunks, so a frame's ~130k entries
+                                 // spread over ~130 workgroups (offsets 16.2 -> 12.4 us against 8)
 constexpr int kChunk = kNT * kItems;
 constexpr int kTopNT = 1024;
 

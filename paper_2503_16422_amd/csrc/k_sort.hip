@@ -528,12 +528,10 @@ constexpr int64_t kRangesSearchAbove = 2048;
 
 }  // namespace
 
-// Keys per thread: small sorts use short chunks so that more blocks run; up to
-// 2^21 keys the chunk equals the emission window (2048), so a tile sort of
-// that size takes its first histogram from the emission.
-inline int sort_kpt(int64_t n_max) {
-    return n_max <= (int64_t(1) << 19) ? 4 : n_max <= (int64_t(1) << 21) ? 8 : 16;
-}
+// Keys per thread: up to 2^21 keys short chunks (1024) so that more blocks run,
+// above long ones (4096); either way the chunk is a multiple of the emission
+// window, so a tile sort takes its first histogram from the emission.
+inline int sort_kpt(int64_t n_max) { return n_max <= (int64_t(1) << 21) ? 4 : 16; }
 
 size_t sort_scratch_bytes(int64_t n_max, int64_t hist_cols) {
     const int64_t chunk = (int64_t)sort_kpt(n_max) * kNT;
