@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     constexpr int kWords = BATCH / 64;
     __shared__ uint64_t s_bits[kBits ? C::NW * kWords : 1];
     const bool cull = a.rp.tile_cull != 0;
-    // per staged record three float4: gx, q s, c0, kx | log2 opacity, q, r, g | b, gy, -, id
+    // per staged record three float4: gx, q s, c0, kx | log2 opacity, q, r, g | b, gy, opacity, id
     __shared__ float4 s_rec[3 * BATCH];
     __shared__ float s_acc[BATCH * kVals];   // per-Gaussian sums of the tile
     const int tile = blockIdx.x;
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
                 const ExpRec q = stage_exp(r, ox, oy);
                 s_rec[3 * k] = make_float4(q.gx, q.s, q.c0, q.kx);
                 s_rec[3 * k + 1] = make_float4(q.lo, q.q, r.c.x, r.c.y);
-                s_rec[3 * k + 2] = make_float4(r.c.z, q.gy, 0.0f, __uint_as_float(id));
+                s_rec[3 * k + 2] = make_float4(r.c.z, q.gy, r.b.w, __uint_as_float(id));
                 if constexpr (kBits) {
                     if (cull) cells = reached_cells<TW, TH, PPT>(r, a.rp, tx * TW, ty * TH);
                 }
@@ -254,14 +254,15 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
             if (!nz) continue;
             const float4 g = s_rec[3 * k];       // gx, q s, c0, kx
             const float q = s_rec[3 * k + 1].y;
-            const uint32_t id = __float_as_uint(s_rec[3 * k + 2].w);
+            const float4 e = s_rec[3 * k + 2];   // b, gy, opacity, id
+            const uint32_t id = __float_as_uint(e.w);
             float out[kVals];
             out[0] = -2.0f * kLn2 * (g.w * m[1] - g.y * m[2]);   // d u
             out[1] = 2.0f * kLn2 * q * m[2];                     // d v
             out[2] = -0.5f * m[3];                               // d conic a
             out[3] = -m[4];                                      // d conic b
             out[4] = -0.5f * m[5];                               // d conic c
-            out[5] = m[0] / a.rec[id].b.w;                       // d opacity
+            out[5] = m[0] / e.z;                                 // d opacity
             out[6] = m[6];
             out[7] = m[7];
             out[8] = m[8];
