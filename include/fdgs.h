@@ -24,9 +24,10 @@
  *   - A context owns scratch memory and is not thread-safe: use one context per
  *     host thread / stream.  Scratch grows geometrically when a call needs more
  *     (hipMalloc, which may wait for the device); a replaced block is freed
- *     only after a later device-wide synchronisation (fdgs_destroy, or once
- *     more than 1 GiB of replaced blocks wait), so growth in one context does
- *     not stall work in flight on other streams.
+ *     only after a later device-wide synchronisation (fdgs_destroy, once
+ *     more than 1 GiB of replaced blocks wait, or when an allocation runs out
+ *     of memory, which then retries, at the exact size if need be), so growth
+ *     in one context does not stall work in flight on other streams.
  *   - Model tensors are float32 structure-of-arrays with plane stride n
  *     (see fdgs_model).  Non-finite parameters or a quaternion with
  *     |q|^2 < 1e-12 make a Gaussian invisible; they never raise an error.

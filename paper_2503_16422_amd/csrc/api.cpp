@@ -50,9 +50,9 @@ struct Buf {
 // Blocks replaced by a larger one.  Kernels enqueued before the growth (on
 // whatever stream the caller gave) may still read the old block, so it is not
 // freed at once: it waits here until a device-wide synchronisation that
-// starts after its retirement -- fdgs_destroy, or a growth that finds more
-// than kRetiredLimit bytes waiting -- so that a growth does not stall every
-// stream of the process.  Growth is geometric (1.5x), so a buffer retires a
+// starts after its retirement -- fdgs_destroy, a growth that finds more than
+// kRetiredLimit bytes waiting, or an allocation that runs out of memory -- so
+// that a growth does not stall every stream of the process.  Growth is geometric (1.5x), so a buffer retires a
 // few blocks at most.
 std::mutex g_retired_mu;
 std::vector<std::pair<int, void *>> g_retired;   // (device, block)
@@ -108,12 +108,30 @@ hipError_t ensure(Buf &b, size_t bytes) {
             if (e != hipSuccess) return e;
         }
     }
-    hipError_t e = hipMalloc(&b.p, want);
+    size_t got = want;
+    hipError_t e = hipMalloc(&b.p, got);
+    if (e == hipErrorOutOfMemory) {
+        // out of memory: free the retired blocks (a device synchronisation), then
+        // try again, at the exact size if the geometric one still does not fit
+        (void)hipGetLastError();
+        bool waiting = false;
+        {
+            std::lock_guard<std::mutex> lk(g_retired_mu);
+            waiting = !g_retired.empty();
+        }
+        e = waiting ? free_retired() : hipErrorOutOfMemory;
+        if (e == hipSuccess) e = hipMalloc(&b.p, got);
+        if (e == hipErrorOutOfMemory && want > bytes) {
+            (void)hipGetLastError();
+            got = bytes;
+            e = hipMalloc(&b.p, got);
+        }
+    }
     if (e != hipSuccess) {
         b.p = nullptr;
         return e;
     }
-    b.cap = want;
+    b.cap = got;
     return hipSuccess;
 }
 
