@@ -185,7 +185,8 @@ def timed_fps_pipelined(ctxs, outs, model, cams, frames, masks, frame_window, cf
     beside another frame's compositor.  Every frame is rendered whole; the
     timed region is bracketed by device-wide synchronisations."""
     import torch
-    streams = [torch.cuda.Stream() for _ in ctxs]      # default priority
+    from paper_2503_16422_amd.render import _own_stream
+    streams = [_own_stream(c) for c in ctxs]           # one per context, reused (default priority)
 
     def run(k0, n):
         for k in range(k0, k0 + n):
@@ -419,7 +420,8 @@ def fwd_bwd(ctx, steps, warmup, streams=3):
     # view's adjoint; the adjoints stay in view order (identical gradients)
     ms = ms_one
     if streams > 1:
-        ctxs = [ctx] + [Context(0) for _ in range(streams - 1)]
+        # contexts of their own, created together, so that their streams are too
+        ctxs = [Context(0) for _ in range(streams)]
         pviews = [(cams[c], t, None, None) for c, t in views]
         pstates = [None] * len(views)
 
@@ -440,7 +442,7 @@ def fwd_bwd(ctx, steps, warmup, streams=3):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         for st in pstates:
             st.release()
-        for c in ctxs[1:]:
+        for c in ctxs:
             c.close()
     ctx.profile(True, count_pairs=True)
     for _ in range(3):
