@@ -131,10 +131,10 @@ typedef struct {
                                    rectangle that its footprint ellipse
                                    reaches; 0: in every tile of the
                                    rectangle.  The image is the same     [1] */
-    int32_t schedule;           /* compositor schedule: 0 one workgroup per
-                                   tile in raster order; 1 persistent
-                                   workgroups take (view, tile) items
-                                   longest list first.  Same image        [0] */
+    int32_t schedule;           /* compositor schedule: one workgroup per
+                                   (view, tile) item, 0 in raster order, 1
+                                   longest list first (a first launch sorts
+                                   the items by list length).  Same image [0] */
     int64_t instance_capacity;  /* 0: size tile-list buffers exactly (one
                                    host synchronisation per frame); >0: fixed
                                    capacity, no synchronisation, overflow

@@ -168,7 +168,7 @@ struct fdgs_state {
     Buf tkeys, tids, tkeys2, tids2;
     // per tile / pixel
     Buf ranges, T_final, n_contrib;
-    Buf sched;         // uint32[V x tiles + 1]: persistent compositor order and work counter
+    Buf sched;         // uint32[V x tiles]: the compositor's longest-first item order
     Buf counts;        // int64[4]: n_vis, n_inst
     Buf g2d;
     Buf scratch;
@@ -732,7 +732,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     uint32_t *bwork = by_buckets ? S->bucket.as<uint32_t>() : nullptr;
     HIP_TRY(ensure(S->counts, sizeof(int64_t) * 4));
     HIP_TRY(ensure(S->ranges, sizeof(uint32_t) * 2 * n_keys));
-    if (cfg->schedule) HIP_TRY(ensure(S->sched, sizeof(uint32_t) * (n_keys + 1)));
+    if (cfg->schedule) HIP_TRY(ensure(S->sched, sizeof(uint32_t) * n_keys));
     if (need_state) {
         HIP_TRY(ensure(S->T_final, sizeof(float) * npx));
         HIP_TRY(ensure(S->n_contrib, sizeof(uint32_t) * npx));

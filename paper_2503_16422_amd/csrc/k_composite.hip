@@ -38,8 +38,7 @@ struct CompArgs {
     unsigned long long *pairs;   // optional counters: evaluated pairs, then blended pairs
     int32_t ppt;                 // pixels per thread (host-side dispatch only)
     int32_t V;                   // views sharing the launch
-    const uint32_t *order;       // persistent schedule: (view, tile) items, longest list first
-    uint32_t *work_counter;      // persistent schedule: next item to take (zeroed by the ordering kernel)
+    const uint32_t *order;       // longest-first schedule: (view, tile) items, longest list first
     int32_t n_items;             // V x tiles per view
     uint8_t *contrib;            // kMark: per processed entry, set to 1 when blended
     float *weight;               // kWeight: per processed entry, += sum of alpha T
@@ -321,32 +320,24 @@ __device__ __forceinline__ void composite_item(const CompArgs &a, int item, floa
     }
 }
 
-// Grid schedule: workgroup b renders item b (tiles in raster order, views in
-// turn).  Persistent schedule: a grid sized to the resident workgroups takes
-// items from a.order (longest tile list first, so the long lists do not start
-// last and leave the device idle at the end) through an atomic counter; every
-// workgroup leaves once the counter passes the item count.  With up to two
-// pixels per thread the register budget is held to eight wavefronts per SIMD
-// (where the LDS allows as many); four pixels need more registers than that.
-template <int TW, int TH, int BATCH, int PPT, int MODE, bool PERSIST>
+// One workgroup per (view, tile) item.  Raster schedule (ORDERED false):
+// workgroup b renders item b (tiles in raster order, views in turn).
+// Longest-first schedule (ORDERED true): workgroup b renders item a.order[b],
+// the items sorted by list length, longest first.  A launch lasts at least as
+// long as its longest lists; dispatched first, they run beside the rest of
+// the launch instead of alone at its end (headline frame: 110 -> 92 us at LDS
+// batch 512).  Workgroups go to the XCDs in turn, so the longest lists are
+// spread over all of them.  With up to two pixels per thread the register
+// budget is held to eight wavefronts per SIMD (where the LDS allows as many);
+// four pixels need more registers than that.
+template <int TW, int TH, int BATCH, int PPT, int MODE, bool ORDERED>
 __global__ void __launch_bounds__(TW *TH / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 4 ? 1 : 8)))
 composite_kernel(CompArgs a) {
     // per staged record three float4 at one address: gx, s, c0, kx |
     // log2 opacity, q, r, g | b, id, -, - (the exponent's staged form)
     __shared__ float4 s_rec[3 * BATCH];
-    if constexpr (!PERSIST) {
-        composite_item<TW, TH, BATCH, PPT, MODE>(a, blockIdx.x, s_rec);
-    } else {
-        __shared__ int s_item;
-        for (;;) {
-            if (threadIdx.x == 0) s_item = (int)atomicAdd(a.work_counter, 1u);
-            __syncthreads();
-            const int it = s_item;
-            __syncthreads();   // s_item is rewritten only after every thread has read it
-            if (it >= a.n_items) break;
-            composite_item<TW, TH, BATCH, PPT, MODE>(a, (int)a.order[it], s_rec);
-        }
-    }
+    const int item = ORDERED ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
+    composite_item<TW, TH, BATCH, PPT, MODE>(a, item, s_rec);
 }
 
 // Visibility flags (bytes) to LSB-first bit words: one ballot per wavefront.
@@ -359,53 +350,41 @@ __global__ void __launch_bounds__(256) flags_to_bits_kernel(const uint8_t *flags
         bits[word] = lane == 0 ? (uint32_t)(m & 0xffffffffu) : (uint32_t)(m >> 32);
 }
 
-// Orders the V x tiles items by the bit length of their list length, longest
-// first (one workgroup; order inside a length class is arbitrary, which only
-// affects scheduling), and zeroes the persistent work counter.
+// Orders the V x tiles items by the length of their lists, longest first, in
+// classes a quarter of an octave wide (bit length and the two bits after the
+// leading one; one workgroup; order inside a class is arbitrary, which only
+// affects scheduling).
 constexpr int kOrderNT = 1024;
 __global__ void __launch_bounds__(kOrderNT) tile_order_kernel(const uint32_t *ranges, int32_t n_items,
-                                                              uint32_t *order, uint32_t *work_counter) {
-    __shared__ uint32_t s_cnt[33];
-    if (threadIdx.x < 33) s_cnt[threadIdx.x] = 0;
+                                                              uint32_t *order) {
+    constexpr int kClasses = 33 * 4;
+    __shared__ uint32_t s_cnt[kClasses];
+    if (threadIdx.x < kClasses) s_cnt[threadIdx.x] = 0;
     __syncthreads();
     auto cls = [&](int i) {
         const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
-        return len ? 32 - __clz(len) : 0;   // 0 (empty) .. 32
+        const int b = len ? 32 - __clz(len) : 0;   // bit length, 0 (empty) .. 32
+        return b * 4 + (b >= 3 ? (int)((len >> (b - 3)) & 3u) : 0);
     };
     for (int i = threadIdx.x; i < n_items; i += kOrderNT) atomicAdd(&s_cnt[cls(i)], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t run = 0;
-        for (int c = 32; c >= 0; --c) {
+        for (int c = kClasses - 1; c >= 0; --c) {
             const uint32_t k = s_cnt[c];
             s_cnt[c] = run;
             run += k;
         }
-        *work_counter = 0u;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n_items; i += kOrderNT) order[atomicAdd(&s_cnt[cls(i)], 1u)] = (uint32_t)i;
-}
-
-// Workgroups of one kernel that fit on the device at once.
-template <typename K>
-int resident_groups(K kernel, int threads) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
-        return 0;
-    return cus * per_cu;
 }
 
 template <int TW, int TH, int BATCH, int PPT, int MODE>
 void launch_fwd_sched(const CompArgs &a, int n_items, hipStream_t s) {
     constexpr int NT = TW * TH / PPT;
     if (a.order) {
-        auto k = composite_kernel<TW, TH, BATCH, PPT, MODE, true>;
-        static const int groups = resident_groups(k, NT);
-        const int grid = groups > 0 ? std::min(groups, n_items) : n_items;
-        hipLaunchKernelGGL(k, dim3(std::max(grid, 1)), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT, MODE, true>), dim3(n_items), dim3(NT), 0, s, a);
     } else {
         hipLaunchKernelGGL((composite_kernel<TW, TH, BATCH, PPT, MODE, false>), dim3(n_items), dim3(NT), 0, s, a);
     }
@@ -450,9 +429,8 @@ hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_
     const bool side = contrib || weight;   // visibility or score pass: no state, no counters
     CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, side ? nullptr : n_contrib,
                side ? nullptr : reinterpret_cast<unsigned long long *>(pair_counter), ppt, V,
-               sched, sched ? sched + n_tiles : nullptr, n_tiles, contrib, contrib ? nullptr : weight};
-    if (sched) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderNT), 0, s, ranges, n_tiles, sched,
-                                  sched + n_tiles);
+               sched, n_tiles, contrib, contrib ? nullptr : weight};
+    if (sched) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderNT), 0, s, ranges, n_tiles, sched);
     FDGS_DISPATCH(launch_fwd, a);
     return hipGetLastError();
 }
