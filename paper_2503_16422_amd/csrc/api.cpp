@@ -160,6 +160,7 @@ struct fdgs_state {
     fdgs_ctx *owner = nullptr;
     bool has_forward = false;
     bool has_g2d = false;   // a backward's first phase ran since the last forward
+    bool ordered = false;   // sched holds the last forward's tiles longest list first
     // per processed Gaussian
     Buf rec, depth_key, rect, tiles, visible, vis_pos, order_k, order_v, order_k2, order_v2, offsets, view_of;
     Buf bucket;        // depth buckets: counts, cursors, starts, key range
@@ -852,6 +853,7 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
     S->rp = rp;
     S->batch = cfg->batch;
     S->ppt = ppt;
+    S->ordered = cfg->schedule == 1;   // its compositor ordered the tiles into sched
     S->capacity = capacity;
     S->W = W;
     S->H = H;
@@ -1173,9 +1175,17 @@ fdgs_status enqueue_backward_2d(fdgs_ctx *ctx, fdgs_state *S, const float *dL_dr
     HIP_TRY(ensure(S->g2d, sizeof(float) * 9 * std::max<int64_t>(S->n_max, 1)));
     StageTimer tm(ctx, FDGS_STAGE_BWD_COMPOSITE, stream);
     HIP_TRY(launch_fill_u32(S->g2d.as<uint32_t>(), 9 * std::max<int64_t>(S->n_max, 1), 0u, stream));
+    // the adjoint takes the tiles longest list first: the forward's order when it
+    // made one, else one made here
+    const int32_t n_tiles = S->rp.tiles_x * S->rp.tiles_y;
+    if (!S->ordered) {
+        HIP_TRY(ensure(S->sched, sizeof(uint32_t) * std::max<int32_t>(n_tiles, 1)));
+        HIP_TRY(launch_tile_order(S->ranges.as<uint32_t>(), n_tiles, S->sched.as<uint32_t>(), stream));
+        S->ordered = true;
+    }
     HIP_TRY(launch_composite_backward(S->rp, S->W, S->H, S->batch, S->ppt, S->ranges.as<uint32_t>(), S->sorted_ids,
                                       S->rec.as<Rec2D>(), S->T_final.as<float>(), S->n_contrib.as<uint32_t>(),
-                                      dL_drgb, S->g2d.as<float>(), S->n_max, stream));
+                                      dL_drgb, S->g2d.as<float>(), S->n_max, S->sched.as<uint32_t>(), stream));
     S->has_g2d = true;
     return FDGS_OK;
 }

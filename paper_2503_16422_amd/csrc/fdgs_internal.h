@@ -156,7 +156,10 @@ hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t 
                                      const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                                      const float *T_final, const uint32_t *n_contrib,
                                      const float *dL_drgb, float *g2d, int64_t n_proc_max,
-                                     hipStream_t s);
+                                     const uint32_t *order, hipStream_t s);
+// order[0 .. n_items): the items of ranges sorted by list length, longest first
+// (the order of the compositors' longest-first schedule).
+hipError_t launch_tile_order(const uint32_t *ranges, int32_t n_items, uint32_t *order, hipStream_t s);
 hipError_t launch_preprocess_backward(const KModel &m, const uint32_t *idx, const int64_t *n_dev,
                                       int64_t n_max, const KCam &cam, double t,
                                       const RenderParams &rp, const uint32_t *vis_list,

@@ -435,6 +435,11 @@ hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_
     return hipGetLastError();
 }
 
+hipError_t launch_tile_order(const uint32_t *ranges, int32_t n_items, uint32_t *order, hipStream_t s) {
+    if (n_items > 0) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderNT), 0, s, ranges, n_items, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_flags_to_bits(const uint8_t *flags, int64_t n, uint32_t *bits, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(flags_to_bits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, flags, n, bits);
     return hipGetLastError();

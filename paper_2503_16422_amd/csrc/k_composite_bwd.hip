@@ -21,6 +21,7 @@ struct BwdArgs {
     const uint32_t *n_contrib;
     const float *dL;
     float *g2d;        // [n_proc][9]: du, dv, d conic a, b, c, d opacity, d rgb
+    const uint32_t *order;   // tiles longest list first (workgroup b takes tile order[b]), or NULL: raster order
 };
 
 // Adjoint, walking each pixel's list back to front from its last contributor.
@@ -70,7 +71,9 @@ __global__ void __launch_bounds__(TW *TH / PPT) composite_bwd_kernel(BwdArgs a) 
     // per staged record three float4: gx, q s, c0, kx | log2 opacity, q, r, g | b, gy, opacity, id
     __shared__ float4 s_rec[3 * BATCH];
     __shared__ float s_acc[BATCH * kVals];   // per-Gaussian sums of the tile
-    const int tile = blockIdx.x;
+    // the longest lists first, as in the forward's longest-first schedule: they
+    // run beside the rest of the launch instead of alone at its end
+    const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile % a.rp.tiles_x, ty = tile / a.rp.tiles_x;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = lane_id();
     const int lx = (wave % C::CX) * C::CW + lane % C::CW, ly0 = (wave / C::CX) * C::CH + (lane / C::CW) * PPT;
@@ -297,8 +300,8 @@ hipError_t launch_composite_backward(const RenderParams &rp, int32_t W, int32_t 
                                      const uint32_t *ranges, const uint32_t *ids, const Rec2D *rec,
                                      const float *T_final, const uint32_t *n_contrib,
                                      const float *dL_drgb, float *g2d, int64_t /*n_proc_max*/,
-                                     hipStream_t s) {
-    BwdLaunch l{BwdArgs{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d}, ppt};
+                                     const uint32_t *order, hipStream_t s) {
+    BwdLaunch l{BwdArgs{rp, W, H, ranges, ids, rec, T_final, n_contrib, dL_drgb, g2d, order}, ppt};
     const int n_tiles = rp.tiles_x * rp.tiles_y;
     FDGS_DISPATCH(launch_bwd, l);
     return hipGetLastError();
