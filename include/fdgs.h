@@ -134,7 +134,7 @@ typedef struct {
     int32_t schedule;           /* compositor schedule: one workgroup per
                                    (view, tile) item, 0 in raster order, 1
                                    longest list first (a first launch sorts
-                                   the items by list length).  Same image [0] */
+                                   the items by list length).  Same image [1] */
     int64_t instance_capacity;  /* 0: size tile-list buffers exactly (one
                                    host synchronisation per frame); >0: fixed
                                    capacity, no synchronisation, overflow

@@ -282,7 +282,7 @@ void fdgs_render_cfg_default(fdgs_render_cfg *cfg) {
     cfg->dilation = 0.3f;
     cfg->temporal_cull = 1;
     cfg->tile_cull = 1;
-    cfg->schedule = 0;
+    cfg->schedule = 1;
     cfg->instance_capacity = 0;
 }
 

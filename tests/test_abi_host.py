@@ -36,7 +36,7 @@ def test_version_and_defaults(lib):
     assert b"gfx950" in lib.fdgs_version()
     cfg = _lib.default_cfg()
     assert (cfg.tile_w, cfg.tile_h, cfg.batch) == (16, 16, 128)
-    assert abs(cfg.alpha_min - 1 / 255) < 1e-8 and cfg.temporal_cull == 1 and cfg.tile_cull == 1 and cfg.schedule == 0
+    assert abs(cfg.alpha_min - 1 / 255) < 1e-8 and cfg.temporal_cull == 1 and cfg.tile_cull == 1 and cfg.schedule == 1
 
 
 def test_null_context_rejected_without_gpu(lib):
