@@ -468,7 +468,7 @@ enum {
     FDGS_STAGE_OFFSETS = 3,      /* instance offsets (scan)                  */
     FDGS_STAGE_DUPLICATE = 4,    /* tile-key emission                        */
     FDGS_STAGE_TILE_SORT = 5,    /* tile radix sort                          */
-    FDGS_STAGE_RANGES = 6,       /* tile ranges                              */
+    FDGS_STAGE_RANGES = 6,       /* tile ranges (and the longest-first order) */
     FDGS_STAGE_COMPOSITE = 7,    /* per-tile blending                        */
     FDGS_STAGE_BWD_COMPOSITE = 8,
     FDGS_STAGE_BWD_PREPROCESS = 9,

@@ -832,6 +832,9 @@ fdgs_status run_forward(fdgs_ctx *ctx, fdgs_state *S, const ViewDesc *one, const
         StageTimer tm(ctx, FDGS_STAGE_RANGES, stream);
         HIP_TRY(launch_tile_ranges(S->sorted_keys, counts + 1, capacity, (int32_t)n_keys, S->ranges.as<uint32_t>(),
                                    stream));
+        // the longest-first schedule's item order, from the ranges
+        if (cfg->schedule == 1)
+            HIP_TRY(launch_tile_order(S->ranges.as<uint32_t>(), (int32_t)n_keys, S->sched.as<uint32_t>(), stream));
     }
     float *T_out = need_state ? S->T_final.as<float>() : out_T;
     uint64_t *acc = nullptr;

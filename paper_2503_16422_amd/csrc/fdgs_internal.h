@@ -131,8 +131,8 @@ hipError_t launch_accumulate_counts(const int64_t *n_proc_dev, int64_t n_proc, c
 // V views of W x H share one tile grid: item i renders tile i % n_tiles of
 // view i / n_tiles; view v writes out_rgb + v*3*W*H (out_T, n_contrib: + v*W*H).
 // sched == NULL: one workgroup per item in item order.  Otherwise sched holds
-// V * n_tiles uint32 of scratch: a first launch orders the items longest list
-// first there, and workgroup b renders the b-th of them.
+// the V * n_tiles items longest list first (launch_tile_order), and workgroup b
+// renders the b-th of them.
 // contrib (optional): contrib[id] = 1 for every processed entry some pixel
 // blends; weight (optional): weight[id] += the entry's summed blend weights
 // alpha T (state and counters are not recorded in either case).

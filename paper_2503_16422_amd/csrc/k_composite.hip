@@ -430,7 +430,6 @@ hipError_t launch_composite(const RenderParams &rp, int32_t W, int32_t H, int32_
     CompArgs a{rp, W, H, ranges, ids, rec, out_rgb, out_T, side ? nullptr : n_contrib,
                side ? nullptr : reinterpret_cast<unsigned long long *>(pair_counter), ppt, V,
                sched, n_tiles, contrib, contrib ? nullptr : weight};
-    if (sched) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderNT), 0, s, ranges, n_tiles, sched);
     FDGS_DISPATCH(launch_fwd, a);
     return hipGetLastError();
 }
