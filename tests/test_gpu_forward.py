@@ -356,8 +356,9 @@ def test_temporal_mask_render_identical_to_dense(ctx):
 # full-size parity ----------------------------------------------------------------------
 # Launch configurations the benchmark's autotuner picks at 1352x1014 (tile,
 # LDS batch, pixels per thread, schedule), besides the default one.
-BENCH_CONFIGS = (((32, 32), 1024, 2, 1), ((32, 32), 512, 2, 1), ((32, 32), 256, 2, 1), ((32, 32), 256, 2, 0),
-                 ((32, 16), 256, 2, 0), ((16, 16), 256, 2, 0), ((32, 32), 1024, 2, 0))
+BENCH_CONFIGS = (((32, 32), 1024, 2, 1), ((32, 32), 512, 2, 1), ((32, 32), 256, 2, 1), ((32, 32), 128, 2, 1),
+                 ((32, 16), 256, 2, 1), ((32, 16), 128, 2, 1), ((32, 32), 256, 2, 0), ((32, 16), 256, 2, 0),
+                 ((16, 16), 256, 2, 0), ((32, 32), 1024, 2, 0))
 
 
 @pytest.mark.parametrize("f,c", [(137, 11), (5, 0)])
@@ -549,18 +550,18 @@ def test_frames_in_flight_on_four_streams_match_one(ctx):
         assert torch.equal(outs[k], ref[k]), k
 
 
-def test_headline_frames_in_flight_on_three_streams_match_one(ctx):
+def test_headline_frames_in_flight_on_four_streams_match_one(ctx):
     """The benchmark's frame loop at full size: masked 1352x1014 frames of the
-    200k-Gaussian scene dealt round-robin to three contexts on three streams,
-    in the benchmark's launch configuration, equal the one-context frames bit
-    for bit."""
+    200k-Gaussian scene dealt round-robin to four contexts on four streams,
+    in a launch configuration the benchmark picks (32x32 tiles, LDS batch 512,
+    longest list first), equal the one-context frames bit for bit."""
     from paper_2503_16422_amd.render import Context
     sc = inputs.long_scene(200_000, seed=0)
     cams = inputs.arc_cameras(20, 4.0, 1352, 1014)
     model = to_dev(sc)
     frames = inputs.frame_times(300)
     keys, windows, fw = inputs.keyframe_windows(300, 10)
-    picks = [(40, 2), (41, 9), (42, 17), (43, 3), (44, 12), (45, 19)]
+    picks = [(40, 2), (41, 9), (42, 17), (43, 3), (44, 12), (45, 19), (46, 6), (47, 14)]
     masks = {}
     for f, _ in picks:
         w = fw[f]
@@ -568,13 +569,13 @@ def test_headline_frames_in_flight_on_three_streams_match_one(ctx):
             lo, hi = windows[w]
             _, idx, count = ctx.build_active_mask(model, frames[lo:hi + 1], frames[lo], frames[hi], 1, cams)
             masks[w] = (idx, count)
-    cfg = _lib.default_cfg(tile_w=32, tile_h=32, batch=1024, pixels_per_thread=2, schedule=1,
+    cfg = _lib.default_cfg(tile_w=32, tile_h=32, batch=512, pixels_per_thread=2, schedule=1,
                            instance_capacity=1 << 22)
     ref = []
     for f, c in picks:
         idx, count = masks[fw[f]]
         ref.append(ctx.render(model, cams[c], float(frames[f]), cfg, idx=idx, n_idx=count)[0].clone())
-    others = [Context(0) for _ in range(2)]
+    others = [Context(0) for _ in range(3)]
     ctxs = [ctx] + others
     streams = [torch.cuda.Stream() for _ in ctxs]
     outs = torch.empty((len(picks), 3, 1014, 1352), device="cuda")
